@@ -1,0 +1,174 @@
+/*
+ * lib_llgdisk: the thin-film LLG disk hot path on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: G. M. Wysin and W. Figueiredo, "Thermal vortex dynamics in thin
+ * circular ferromagnetic nanodisks" (2012).  A disk of radius R and thickness
+ * L is cut into a x a x L cells on a square grid (Sec. II.A); each cell holds
+ * a unit vector m_i.  The demagnetisation field is the convolution of m with
+ * the 2-D thin-film Green's kernels (Sec. II.B), evaluated by zero-padded FFT;
+ * the induction b adds the nearest-neighbour exchange sum (eq. Bi); the
+ * dynamics is dm/dtau = m x b - alpha m x (m x b) (Sec. III.A), stepped by RK4
+ * at T = 0 (Sec. III.A) and by the Heun (H2) scheme with thermal noise at
+ * T > 0 (Sec. III.B-C).
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * Handle.  An llg_disk owns one disk or a batch of disks (replicas included),
+ *   with their kernel spectra, twiddle tables, workspaces and barrier counters
+ *   in device memory on the device that was current when it was created.  It
+ *   is not thread-safe; calls on one handle must not overlap.
+ * State layout.  The magnetisation of disk k is float32 [3][D_k][D_k]
+ *   (component x, y, z; row = y cell index, column = x cell index); cell
+ *   (iy, ix) sits at ((ix-(D-1)/2) a, (iy-(D-1)/2) a) from the disk centre and
+ *   belongs to the disk when that point lies inside the circle of radius R.
+ *   For a batch the disks are packed back to back in creation order; disk k
+ *   starts at float offset llg_disk_offset(h, k).  Values outside the disk are
+ *   ignored on input and written as 0 on output.
+ * Pointers.  Every float and double array argument is a caller-owned DEVICE
+ *   pointer on the handle's device, unless the comment says "host".  The
+ *   library never frees or keeps them past the call.  llg_params arrays are
+ *   host memory (one entry per disk of the handle).
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = the default
+ *   stream).  All work is enqueued asynchronously on it; results are ready
+ *   when the stream reaches them.  Only llg_build_kernels, llg_batch_create
+ *   and llg_check synchronise.
+ * Units.  Lengths cross the ABI in nm.  Fields are in units of Ms, the
+ *   induction b in units of B0 = 2A/(a^2 Ms), time in units of
+ *   t0 = 1/(gamma B0), energies in units of J = 2AL of each disk.
+ * Errors.  Every int-returning call returns 0 on success or a negative LLG_E*
+ *   code; the message is available from llg_last_error() (per thread).  A
+ *   device-side failure (a group barrier that timed out, a non-finite state)
+ *   is recorded on the device and reported by the next llg_check().
+ */
+#ifndef LLGDISK_H
+#define LLGDISK_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LLG_OK 0
+#define LLG_EINVAL (-1)    /* bad argument (geometry, sizes, null pointer) */
+#define LLG_EHIP (-2)      /* a HIP runtime call failed */
+#define LLG_ENOMEM (-3)    /* device or host allocation failed */
+#define LLG_EDEVICE (-4)   /* device-side failure flag raised (llg_check) */
+#define LLG_EUNSUPPORTED (-5)
+
+typedef struct llg_disk_s* llg_disk;
+
+/* Dimensionless parameters of one disk (Sec. II.A, Sec. III).
+ *   alpha     Gilbert damping.
+ *   c         a^2/lambda_ex^2; multiplies the demag and external fields in b (eq. Bi).
+ *   hext      external field / Ms.
+ *   temp      scaled temperature kT/(2AL) (Sec. III.B).
+ *   dtau      time step in units of t0.
+ *   renorm    nonzero: reset |m| = 1 after every full step.
+ *   fd_factor nonzero: noise variance 2 alpha T dtau / (1 + alpha^2) instead of
+ *             the paper's 2 alpha T dtau (Sec. III.C). */
+typedef struct {
+    double alpha;
+    double c;
+    double hext[3];
+    double temp;
+    double dtau;
+    int renorm;
+    int fd_factor;
+} llg_params;
+
+/* Fill *out (host) from SI material data: exchange stiffness A (J/m), Ms (A/m),
+ * gamma (1/(T s)), cell edge a and thickness L (nm), time step dt (ps),
+ * temperature T (K) and damping alpha; hext is set to 0, renorm and fd_factor
+ * to 0.  Also returns lambda_ex in nm through *lambda_ex_nm (host, may be NULL).
+ * Formulas of Sec. II.A and Sec. III.A-B. */
+int llg_params_from_si(double A, double Ms, double gamma, double a_nm, double L_nm,
+                       double dt_ps, double T_K, double alpha, llg_params* out,
+                       double* lambda_ex_nm);
+
+/* Build one disk: D = 2R/a cells across (must be an integer within 1e-9),
+ * mask, and the FFT size P (P_override = 0: the smallest power of two >= 2D,
+ * at least 64; otherwise a power of two in [64, 512] with P >= 2D-1).  The
+ * thin-film kernels (Sec. II.B: G_xx, G_yy, G_xy, G_zz at cell-centre
+ * displacements, self terms -N_x, -N_x, 0, -N_z of the cell cylinder of radius
+ * a/sqrt(pi)) are laid out at wrapped displacements on the P x P grid and
+ * transformed once in float64 on the host; the real spectra are stored as
+ * float32 quarter planes.  Synchronises the current device. */
+int llg_build_kernels(double R_nm, double L_nm, double a_nm, int P_override, llg_disk* out);
+
+/* Build a batch of n disks (a ragged ensemble and/or replicas): disk k has
+ * radius R_nm[k] and thickness L_nm[k] (host arrays), all with cell edge a.
+ * Equal geometries share one set of spectra.  wg_per_disk (host, may be NULL)
+ * fixes the number of workgroups that step each disk; NULL lets the library
+ * choose from the disk's cost and the device size. */
+int llg_batch_create(int n, const double* R_nm, const double* L_nm, double a_nm,
+                     const int* wg_per_disk, llg_disk* out);
+
+/* Host queries: number of disks; D, P and masked-cell count of disk k; float
+ * offset of disk k in a packed state; total floats of a packed state. */
+int llg_disk_count(llg_disk h);
+int llg_disk_info(llg_disk h, int k, int* D, int* P, int* n_cells);
+long long llg_disk_offset(llg_disk h, int k);
+long long llg_state_size(llg_disk h);
+/* Workgroups assigned to disk k (host). */
+int llg_disk_workgroups(llg_disk h, int k);
+
+/* Demagnetisation field H^M / Ms of state m (Sec. II.B): H[k] = sum over the
+ * disk of K(r_i - r_j) m_j, written to H (packed like m). */
+int llg_demag_field(llg_disk h, const float* m, float* H, void* stream);
+
+/* Right-hand side dm/dtau = m x b - alpha m x (m x b) with
+ * b = exchange sum + c (hext + H^M) (eq. Bi, Sec. III.A); p: one entry per disk. */
+int llg_rhs(llg_disk h, const float* m, float* dmdtau, const llg_params* p, void* stream);
+
+/* nsteps classical RK4 steps in place (Sec. III.A), the full field evaluated
+ * at all four stages; |m| reset to 1 after each step when p->renorm is set. */
+int llg_rk4_step(llg_disk h, float* m, long long nsteps, const llg_params* p, void* stream);
+
+/* nsteps Heun (H2) steps in place (Sec. III.C): g = b dtau + sigma w,
+ * Delta(m) = m x [g - alpha (m x g)], predictor m~ = m + Delta(m), corrector
+ * m' = m + (Delta(m) + Delta(m~))/2 with the same w, sigma = sqrt(2 alpha T dtau)
+ * (over 1 + alpha^2 when fd_factor is set).  Step s (= step0 + n) of disk k
+ * draws w for box cell q = iy*D + ix from Philox4x64-10 with counter
+ * (s, q, replica + k, 0) and key (seed, 0); the top 24 bits of the four
+ * outputs give uniforms u0..u3 and w = (sqrt(-2 ln u0) cos 2pi u1,
+ * sqrt(-2 ln u0) sin 2pi u1, sqrt(-2 ln u2) cos 2pi u3). */
+int llg_heun_step(llg_disk h, float* m, long long nsteps, unsigned long long seed,
+                  unsigned long long step0, unsigned int replica, const llg_params* p,
+                  void* stream);
+
+/* The noise w that llg_heun_step uses at one time step (test hook), packed
+ * like m (zero outside the disks). */
+int llg_noise(llg_disk h, unsigned long long seed, unsigned long long step,
+              unsigned int replica, float* w, void* stream);
+
+/* Energy of eq. Hmm in units of J, float64 sums on the device:
+ * out[4k..4k+3] = (E, E_exchange, E_demag, E_external) for disk k with
+ * E_exchange = -sum over neighbour pairs m_i.m_j, E_demag = -(c/2) sum H.m,
+ * E_external = -c sum hext.m. */
+int llg_energy(llg_disk h, const float* m, const llg_params* p, double* out, void* stream);
+
+/* Vortex core position (Sec. IV), float64 on the device.  out[5k..5k+4] =
+ * (x_c, y_c, x_v, y_v, n_plus) in nm from the disk centre: r_v is the shared
+ * corner of a 2x2 plaquette of disk cells whose in-plane angle winds by +1
+ * (angle differences wrapped into [-pi, pi)); with several, the one nearest
+ * hint_nm[2k..2k+1] (host, may be NULL) or else the one with the largest
+ * sum of m_z^2 over its corners, ties to the lowest row then column;
+ * r_c = sum (m_z)^2 r_i / sum (m_z)^2 over disk cells with |r_i - r_v| <
+ * 4 lambda_ex.  With no such plaquette n_plus = 0, r_v = NaN and r_c is the
+ * weighted mean over the whole disk. */
+int llg_vortex_core_position(llg_disk h, const float* m, double lambda_ex_nm,
+                             const double* hint_nm, double* out, void* stream);
+
+/* Spatial average <m> per disk (Sec. IV): out[3k..3k+2], float64. */
+int llg_mean_m(llg_disk h, const float* m, double* out, void* stream);
+
+/* Synchronise the stream and report a device-side failure recorded since the
+ * last check (LLG_EDEVICE) or 0. */
+int llg_check(llg_disk h, void* stream);
+
+void llg_destroy(llg_disk h);
+const char* llg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LLGDISK_H */

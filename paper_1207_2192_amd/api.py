@@ -1,0 +1,224 @@
+"""Python binding of lib_llgdisk: same entry points as include/llgdisk.h.
+
+Only argument marshalling happens here (tensor checks, pointers, the current
+HIP stream); every step of the hot path runs in the library's kernels.  Torch
+supplies device memory and streams.  Arrays are float32 tensors on the
+handle's GPU laid out [3][D][D] per disk and packed back to back for batches.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+
+import torch
+
+from . import _lib
+from ._lib import LLGParamsC, check
+
+
+@dataclass
+class LLGParams:
+    """Dimensionless parameters (see llg_params in include/llgdisk.h)."""
+    alpha: float = 0.0
+    c: float = 0.0
+    hext: tuple = (0.0, 0.0, 0.0)
+    temp: float = 0.0
+    dtau: float = 0.04
+    renorm: bool = False
+    fd_factor: bool = False
+
+    def to_c(self) -> LLGParamsC:
+        p = LLGParamsC()
+        p.alpha, p.c, p.temp, p.dtau = self.alpha, self.c, self.temp, self.dtau
+        for i in range(3):
+            p.hext[i] = float(self.hext[i])
+        p.renorm, p.fd_factor = int(bool(self.renorm)), int(bool(self.fd_factor))
+        return p
+
+
+def params_from_si(A: float, Ms: float, gamma: float, a_nm: float, L_nm: float, dt_ps: float,
+                   T_K: float = 0.0, alpha: float = 0.0):
+    """(LLGParams, lambda_ex_nm) from SI material data via llg_params_from_si."""
+    lib = _lib.load()
+    p = LLGParamsC()
+    lam = ctypes.c_double()
+    check(lib.llg_params_from_si(A, Ms, gamma, a_nm, L_nm, dt_ps, T_K, alpha, ctypes.byref(p),
+                                 ctypes.byref(lam)), "llg_params_from_si")
+    return LLGParams(alpha=p.alpha, c=p.c, hext=tuple(p.hext), temp=p.temp, dtau=p.dtau), lam.value
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Disk:
+    """A disk (or a batch of disks) built by llg_build_kernels / llg_batch_create."""
+
+    def __init__(self, handle, device: torch.device):
+        self._h = handle
+        self.device = device
+        lib = _lib.load()
+        self.n = lib.llg_disk_count(self._h)
+        self.D, self.P, self.n_cells, self.offsets, self.workgroups = [], [], [], [], []
+        for k in range(self.n):
+            D, P, N = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+            check(lib.llg_disk_info(self._h, k, ctypes.byref(D), ctypes.byref(P), ctypes.byref(N)), "llg_disk_info")
+            self.D.append(D.value)
+            self.P.append(P.value)
+            self.n_cells.append(N.value)
+            self.offsets.append(lib.llg_disk_offset(self._h, k))
+            self.workgroups.append(lib.llg_disk_workgroups(self._h, k))
+        self.state_size = lib.llg_state_size(self._h)
+
+    # ---------------------------------------------------------------- creation
+    @classmethod
+    def build(cls, R_nm: float, L_nm: float, a_nm: float = 2.0, P: int = 0) -> "Disk":
+        lib = _lib.load()
+        h = ctypes.c_void_p()
+        dev = torch.device("cuda", torch.cuda.current_device())
+        check(lib.llg_build_kernels(R_nm, L_nm, a_nm, P, ctypes.byref(h)), "llg_build_kernels")
+        return cls(h, dev)
+
+    @classmethod
+    def batch(cls, R_nm, L_nm, a_nm: float = 2.0, wg_per_disk=None) -> "Disk":
+        lib = _lib.load()
+        n = len(R_nm)
+        R = (ctypes.c_double * n)(*[float(r) for r in R_nm])
+        L = (ctypes.c_double * n)(*[float(x) for x in L_nm])
+        W = None if wg_per_disk is None else (ctypes.c_int * n)(*[int(w) for w in wg_per_disk])
+        h = ctypes.c_void_p()
+        dev = torch.device("cuda", torch.cuda.current_device())
+        check(lib.llg_batch_create(n, R, L, a_nm, W, ctypes.byref(h)), "llg_batch_create")
+        return cls(h, dev)
+
+    def close(self):
+        if self._h:
+            _lib.load().llg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- helpers
+    def _state(self, m: torch.Tensor, name="m") -> torch.Tensor:
+        if not isinstance(m, torch.Tensor) or m.device.type != "cuda" or m.dtype != torch.float32:
+            raise TypeError(f"{name} must be a float32 CUDA tensor")
+        if not m.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if m.numel() != self.state_size:
+            raise ValueError(f"{name} has {m.numel()} elements, the handle expects {self.state_size}")
+        return m
+
+    def _params(self, params):
+        if isinstance(params, LLGParams):
+            params = [params] * self.n
+        if len(params) != self.n:
+            raise ValueError(f"need {self.n} parameter sets")
+        arr = (LLGParamsC * self.n)(*[p.to_c() for p in params])
+        return arr
+
+    def unpack(self, flat: torch.Tensor, k: int) -> torch.Tensor:
+        D = self.D[k]
+        o = self.offsets[k]
+        return flat[o:o + 3 * D * D].view(3, D, D)
+
+    def pack(self, states) -> torch.Tensor:
+        return torch.cat([s.reshape(-1) for s in states]).contiguous()
+
+    # ---------------------------------------------------------------- entry points
+    def demag_field(self, m: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        m = self._state(m)
+        H = torch.empty_like(m) if out is None else self._state(out, "out")
+        check(_lib.load().llg_demag_field(self._h, _ptr(m), _ptr(H), _stream()), "llg_demag_field")
+        return H
+
+    def rhs(self, m: torch.Tensor, params, out: torch.Tensor | None = None) -> torch.Tensor:
+        m = self._state(m)
+        f = torch.empty_like(m) if out is None else self._state(out, "out")
+        check(_lib.load().llg_rhs(self._h, _ptr(m), _ptr(f), self._params(params), _stream()), "llg_rhs")
+        return f
+
+    def rk4_step(self, m: torch.Tensor, nsteps: int, params) -> torch.Tensor:
+        m = self._state(m)
+        check(_lib.load().llg_rk4_step(self._h, _ptr(m), int(nsteps), self._params(params), _stream()), "llg_rk4_step")
+        return m
+
+    def heun_step(self, m: torch.Tensor, nsteps: int, params, *, seed: int, step0: int = 0,
+                  replica: int = 0) -> torch.Tensor:
+        m = self._state(m)
+        check(_lib.load().llg_heun_step(self._h, _ptr(m), int(nsteps), int(seed), int(step0), int(replica),
+                                        self._params(params), _stream()), "llg_heun_step")
+        return m
+
+    def noise(self, seed: int, step: int, replica: int = 0) -> torch.Tensor:
+        w = torch.empty(self.state_size, dtype=torch.float32, device=self.device)
+        check(_lib.load().llg_noise(self._h, int(seed), int(step), int(replica), _ptr(w), _stream()), "llg_noise")
+        return w
+
+    def energy(self, m: torch.Tensor, params) -> torch.Tensor:
+        m = self._state(m)
+        out = torch.empty(self.n, 4, dtype=torch.float64, device=self.device)
+        check(_lib.load().llg_energy(self._h, _ptr(m), self._params(params), _ptr(out), _stream()), "llg_energy")
+        return out
+
+    def vortex_core_position(self, m: torch.Tensor, lambda_ex_nm: float, hint_nm=None) -> torch.Tensor:
+        m = self._state(m)
+        out = torch.empty(self.n, 5, dtype=torch.float64, device=self.device)
+        hint = None
+        if hint_nm is not None:
+            flat = [float(v) for xy in hint_nm for v in xy] if self.n > 1 or hasattr(hint_nm[0], "__len__") \
+                else [float(hint_nm[0]), float(hint_nm[1])]
+            hint = (ctypes.c_double * (2 * self.n))(*flat)
+        check(_lib.load().llg_vortex_core_position(self._h, _ptr(m), float(lambda_ex_nm), hint, _ptr(out),
+                                                   _stream()), "llg_vortex_core_position")
+        return out
+
+    def mean_m(self, m: torch.Tensor) -> torch.Tensor:
+        m = self._state(m)
+        out = torch.empty(self.n, 3, dtype=torch.float64, device=self.device)
+        check(_lib.load().llg_mean_m(self._h, _ptr(m), _ptr(out), _stream()), "llg_mean_m")
+        return out
+
+    def check(self):
+        """Synchronise and raise if a device-side failure was recorded."""
+        check(_lib.load().llg_check(self._h, _stream()), "llg_check")
+
+
+# ---------------------------------------------------------------- C-ABI-named functions
+def build_kernels(R_nm: float, L_nm: float, a_nm: float = 2.0, P: int = 0) -> Disk:
+    return Disk.build(R_nm, L_nm, a_nm, P)
+
+
+def batch_create(R_nm, L_nm, a_nm: float = 2.0, wg_per_disk=None) -> Disk:
+    return Disk.batch(R_nm, L_nm, a_nm, wg_per_disk)
+
+
+def demag_field(disk: Disk, m, out=None):
+    return disk.demag_field(m, out)
+
+
+def llg_rhs(disk: Disk, m, params, out=None):
+    return disk.rhs(m, params, out)
+
+
+def rk4_step(disk: Disk, m, nsteps, params):
+    return disk.rk4_step(m, nsteps, params)
+
+
+def heun_step(disk: Disk, m, nsteps, params, *, seed, step0=0, replica=0):
+    return disk.heun_step(m, nsteps, params, seed=seed, step0=step0, replica=replica)
+
+
+def vortex_core_position(disk: Disk, m, lambda_ex_nm, hint_nm=None):
+    return disk.vortex_core_position(m, lambda_ex_nm, hint_nm)
+
+
+def energy(disk: Disk, m, params):
+    return disk.energy(m, params)

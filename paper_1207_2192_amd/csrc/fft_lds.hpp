@@ -1,0 +1,152 @@
+// Stockham radix-R FFT of length P held in LDS, one transform per group of
+// P/R lanes.  Written for gfx950: a workgroup runs three wavefronts (one per
+// field component or packed row pair) that step through identical stage
+// schedules, so every stage boundary is a workgroup barrier and LDS holds one
+// P-point buffer per transform.
+//
+// Forward: X[k] = sum_n x[n] exp(-2 pi i n k / P); inverse uses +i and is not
+// normalised.  Twiddles come from a table W[e] = exp(-2 pi i e / P) computed in
+// float64 on the host and rounded to float32.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace llg {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+    return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+// multiply by -i (forward) or +i (inverse)
+template <bool INV>
+__device__ __forceinline__ float2 rot90(float2 d) {
+    return INV ? make_float2(-d.y, d.x) : make_float2(d.y, -d.x);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft2(float2& a, float2& b) {
+    float2 t = a;
+    a = cadd(t, b);
+    b = csub(t, b);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(float2& x0, float2& x1, float2& x2, float2& x3) {
+    float2 a0 = cadd(x0, x2), a1 = csub(x0, x2);
+    float2 a2 = cadd(x1, x3), a3 = rot90<INV>(csub(x1, x3));
+    x0 = cadd(a0, a2);
+    x2 = csub(a0, a2);
+    x1 = cadd(a1, a3);
+    x3 = csub(a1, a3);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft8(float2* x) {
+    // even/odd split into two 4-point transforms, combined with W8^k
+    float2 e0 = x[0], e1 = x[2], e2 = x[4], e3 = x[6];
+    float2 o0 = x[1], o1 = x[3], o2 = x[5], o3 = x[7];
+    dft4<INV>(e0, e1, e2, e3);
+    dft4<INV>(o0, o1, o2, o3);
+    const float r = 0.70710678118654752440f;
+    // o1 *= W8^1, o2 *= W8^2, o3 *= W8^3 (conjugates for the inverse)
+    float2 t1 = INV ? make_float2(r * (o1.x - o1.y), r * (o1.x + o1.y))
+                    : make_float2(r * (o1.x + o1.y), r * (o1.y - o1.x));
+    float2 t2 = rot90<INV>(o2);
+    float2 t3 = INV ? make_float2(-r * (o3.x + o3.y), r * (o3.x - o3.y))
+                    : make_float2(r * (o3.y - o3.x), -r * (o3.x + o3.y));
+    x[0] = cadd(e0, o0);
+    x[4] = csub(e0, o0);
+    x[1] = cadd(e1, t1);
+    x[5] = csub(e1, t1);
+    x[2] = cadd(e2, t2);
+    x[6] = csub(e2, t2);
+    x[3] = cadd(e3, t3);
+    x[7] = csub(e3, t3);
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dftR(float2* x) {
+    if constexpr (R == 2) {
+        dft2<INV>(x[0], x[1]);
+    } else if constexpr (R == 4) {
+        dft4<INV>(x[0], x[1], x[2], x[3]);
+    } else {
+        static_assert(R == 8, "radix 2, 4 or 8");
+        dft8<INV>(x);
+    }
+}
+
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+
+// One length-P transform by the lanes t = 0 .. P/R-1 of a lane group.
+// On entry v[j] = x[t + j*(P/R)].  On exit buf[0..P) holds X in natural
+// order.  buf may alias the input storage; tw is the P-entry twiddle table.
+// Every lane of the workgroup must call this the same number of times
+// (it contains workgroup barriers).
+template <int P, int R, bool INV>
+__device__ __forceinline__ void fft_run(float2 (&v)[R], float2* buf, const float2* tw, int t) {
+    constexpr int Tf = P / R;
+    constexpr int LOGR = ilog2(R);
+    constexpr int LOGP = ilog2(P);
+    constexpr int NFULL = LOGP / LOGR;
+    constexpr int REM = 1 << (LOGP - NFULL * LOGR);
+    int Ns = 1;
+#pragma unroll
+    for (int s = 0; s < NFULL; ++s) {
+        if (s > 0) {
+#pragma unroll
+            for (int j = 0; j < R; ++j) v[j] = buf[t + j * Tf];
+            const int kk = t & (Ns - 1);
+            const int stp = kk * (P / (Ns * R));
+#pragma unroll
+            for (int j = 1; j < R; ++j) {
+                const float2 w = tw[(j * stp) & (P - 1)];
+                v[j] = INV ? cmulc(v[j], w) : cmul(v[j], w);
+            }
+        }
+        dftR<R, INV>(v);
+        const int kk = t & (Ns - 1);
+        const int base = (t - kk) * R + kk;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < R; ++j) buf[base + j * Ns] = v[j];
+        __syncthreads();
+        Ns *= R;
+    }
+    if constexpr (REM > 1) {
+        constexpr int NB = R / REM;
+        float2 u[R];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int k = t + q * Tf;
+            const int kk = k & (Ns - 1);
+            const int stp = kk * (P / (Ns * REM));
+#pragma unroll
+            for (int j = 0; j < REM; ++j) {
+                float2 x = buf[k + j * (P / REM)];
+                if (j > 0) {
+                    const float2 w = tw[(j * stp) & (P - 1)];
+                    x = INV ? cmulc(x, w) : cmul(x, w);
+                }
+                u[q * REM + j] = x;
+            }
+            dftR<REM, INV>(u + q * REM);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int k = t + q * Tf;
+            const int kk = k & (Ns - 1);
+            const int base = (k - kk) * REM + kk;
+#pragma unroll
+            for (int j = 0; j < REM; ++j) buf[base + j * Ns] = u[q * REM + j];
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace llg

@@ -1,0 +1,137 @@
+// Device side of lib_llgdisk: descriptors shared with the host, Philox noise,
+// the group barrier and the persistent field/integrator kernel.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft_lds.hpp"
+
+namespace llg {
+
+constexpr int WG_THREADS = 192;   // three wavefronts: components x, y, z (or packed row pairs)
+constexpr int MAX_P = 512;
+constexpr int MAX_R = 8;
+constexpr int LDS_FFT = 3 * 64 * MAX_R;   // float2 slots: 3 waves x (64/Tf units) x P = 3*64*R
+
+// Per-disk descriptor (device memory, written once by the host).
+struct DiskDesc {
+    int D, P, H, Dp;          // box, FFT size, P/2+1, spectra row stride (D rounded up to even)
+    int n_pairs, G, n_cells, k;  // row pairs, workgroups, masked cells, index in the batch
+    long long m_off;          // float offset of this disk in a packed state
+    float* ya;                // stage state A  [3][D][D]
+    float* yb;                // stage state B  [3][D][D]
+    float* acc;               // RK4 accumulator / Heun predictor increment [3][D][D]
+    float2* S;                // row/column spectra [3][H][Dp]
+    const float* spec;        // kernel spectra quarter planes [4][H][H] (xx, yy, xy, zz) / P^2
+    const unsigned char* mask;  // [D][D]
+    const float2* tw;         // twiddles [P]
+    unsigned int* bar;        // group barrier counter (own cache line)
+    double* part;             // per-workgroup partial sums [G][4]
+};
+
+// Per-disk parameters (device memory, refreshed when they change).
+struct DiskPrm {
+    float alpha, c, hx, hy, hz, dtau, sigma;
+    int renorm;
+    double c_d, hx_d, hy_d, hz_d;
+};
+
+enum Mode : int { MODE_DEMAG = 0, MODE_RHS = 1, MODE_ENERGY = 2, MODE_RK4 = 3, MODE_HEUN = 4 };
+
+enum ErrBits : int { ERR_BARRIER = 1, ERR_NONFINITE = 2 };
+
+struct KArgs {
+    const DiskDesc* disks;
+    const DiskPrm* prm;
+    const int* wg2disk;   // -1 for idle workgroups
+    const int* wg2local;
+    float* m;             // packed state (input, or in/out for the integrators)
+    float* out;           // packed output (demag field or rhs), may be null
+    long long nsteps;
+    unsigned long long seed, step0;
+    unsigned int replica0;
+    int mode;
+    int* err;
+};
+
+// ---------------------------------------------------------------- Philox4x64-10
+// Counter-based generator of Salmon et al. (SC'11): ten rounds of two 64x64->128
+// multiplies mixed with the other counter words and the key; the key is bumped
+// by two Weyl constants between rounds.
+__device__ __forceinline__ void philox4x64_10(uint64_t& c0, uint64_t& c1, uint64_t& c2, uint64_t& c3,
+                                              uint64_t k0, uint64_t k1) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+        const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+}
+
+__device__ __forceinline__ float u24(uint64_t x) {
+    return ((float)(uint32_t)(x >> 40) + 0.5f) * 5.9604644775390625e-08f;  // 2^-24
+}
+
+// Three standard normals for (step, cell, replica) under `seed`.
+__device__ __forceinline__ float3 thermal_normals(unsigned long long seed, unsigned long long step,
+                                                  unsigned long long cell, unsigned long long replica) {
+    uint64_t c0 = step, c1 = cell, c2 = replica, c3 = 0;
+    philox4x64_10(c0, c1, c2, c3, seed, 0ull);
+    const float u0 = u24(c0), u1 = u24(c1), u2 = u24(c2), u3 = u24(c3);
+    const float r01 = sqrtf(-2.0f * logf(u0));
+    const float r23 = sqrtf(-2.0f * logf(u2));
+    float s1, c1f, s3, c3f;
+    sincospif(2.0f * u1, &s1, &c1f);
+    sincospif(2.0f * u3, &s3, &c3f);
+    return make_float3(r01 * c1f, r01 * s1, r23 * c3f);
+}
+
+// ---------------------------------------------------------------- group barrier
+// All workgroups that step one disk meet here.  The counter only grows during
+// a launch (it is cleared before each launch); `target` = epoch * G.  A wait
+// that exceeds the spin budget raises ERR_BARRIER and returns false so that
+// every wave leaves the kernel.
+constexpr unsigned int SPIN_LIMIT = 1u << 22;
+
+__device__ __forceinline__ bool group_barrier(unsigned int* bar, unsigned int target, int G, int* err) {
+    __syncthreads();
+    if (G == 1) return true;
+    __shared__ int s_ok;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned int spins = 0;
+        int ok = 1;
+        while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > SPIN_LIMIT) {
+                ok = 0;
+                __hip_atomic_fetch_or(err, (int)ERR_BARRIER, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+        __threadfence();
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+}  // namespace llg

@@ -1,0 +1,591 @@
+// Kernels of lib_llgdisk.
+//
+// llg_persistent: one cooperative launch steps every disk of a batch.  Each
+// disk is owned by G workgroups that meet at a per-disk group barrier; there
+// is no device-wide barrier, so disks of different sizes progress
+// independently.  One field evaluation (demag + exchange + torque) is three
+// LDS-resident FFT passes fused into two phases:
+//
+//   column phase : for each spectral column kx: forward FFT along y of the
+//                  three row spectra, multiply by the real kernel spectra,
+//                  inverse FFT along y, keep the D rows of the disk.
+//   row phase    : for each pair of rows: inverse FFT along x (two real rows
+//                  and the packed z pair as three complex transforms), the
+//                  exchange sum, the induction b, the torque, the RK4 or Heun
+//                  stage update, and the forward FFT along x of the new stage
+//                  state, unpacked into the row spectra for the next stage.
+//
+// The row spectra live in a [3][P/2+1][D] complex workspace per disk, so a
+// field evaluation moves them through L2/HBM twice per phase pair.
+#pragma once
+#include "llg_device.hpp"
+
+namespace llg {
+
+template <int P, int R>
+__device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, const DiskPrm& pr, int g,
+                                         float2* lds, float2* ltw) {
+    constexpr int Tf = P / R;
+    constexpr int U = 64 / Tf;
+    constexpr int H = P / 2 + 1;
+    const int D = d.D, Dp = d.Dp, G = d.G;
+    const int DD = D * D;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int u = lane / Tf, t = lane - u * Tf;
+    float2* const mybuf = lds + (wave * U + u) * P;
+#define BUF(w, uu) (lds + ((w) * U + (uu)) * P)
+
+    for (int i = threadIdx.x; i < P; i += WG_THREADS) ltw[i] = d.tw[i];
+    __syncthreads();
+
+    float* const m = a.m + d.m_off;
+    float* const out = a.out ? a.out + d.m_off : nullptr;
+    const unsigned char* __restrict__ mask = d.mask;
+    float2* __restrict__ S = d.S;
+    const int n_rb = (d.n_pairs + U - 1) / U;
+    const int n_cb = (H + U - 1) / U;
+    unsigned int epoch = 0;
+    const int mode = a.mode;
+
+    // ---- packed rows of a state into LDS (masked), columns [0, D)
+    auto load_state_rows = [&](int b, const float* src) {
+        for (int idx = threadIdx.x; idx < U * D; idx += WG_THREADS) {
+            const int uu = idx / D, i = idx - uu * D;
+            const int p = b * U + uu, j0 = 2 * p, j1 = j0 + 1;
+            float x0 = 0.f, y0 = 0.f, z0 = 0.f, x1 = 0.f, y1 = 0.f, z1 = 0.f;
+            if (p < d.n_pairs) {
+                const int c0 = j0 * D + i;
+                if (mask[c0]) {
+                    x0 = src[c0];
+                    y0 = src[DD + c0];
+                    z0 = src[2 * DD + c0];
+                }
+                if (j1 < D) {
+                    const int c1 = j1 * D + i;
+                    if (mask[c1]) {
+                        x1 = src[c1];
+                        y1 = src[DD + c1];
+                        z1 = src[2 * DD + c1];
+                    }
+                }
+            }
+            BUF(0, uu)[i] = make_float2(x0, y0);
+            BUF(1, uu)[i] = make_float2(x1, y1);
+            BUF(2, uu)[i] = make_float2(z0, z1);
+        }
+        __syncthreads();
+    };
+
+    // ---- forward transforms along x of the packed rows in LDS; unpack to S
+    auto row_forward_store = [&](int b) {
+        float2 v[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int i = t + j * Tf;
+            v[j] = (i < D) ? mybuf[i] : make_float2(0.f, 0.f);
+        }
+        fft_run<P, R, false>(v, mybuf, ltw, t);
+        for (int idx = threadIdx.x; idx < U * H; idx += WG_THREADS) {
+            const int uu = idx / H, k = idx - uu * H;
+            const int p = b * U + uu;
+            if (p >= d.n_pairs) continue;
+            const int j0 = 2 * p;
+            const int km = (P - k) & (P - 1);
+            const float2 A0 = BUF(0, uu)[k], B0 = BUF(0, uu)[km];
+            const float2 A1 = BUF(1, uu)[k], B1 = BUF(1, uu)[km];
+            const float2 A2 = BUF(2, uu)[k], B2 = BUF(2, uu)[km];
+            // two real rows packed as a + i b:  a^ = (A + conj B)/2,  b^ = (A - conj B)/(2i)
+            const float4 sx = make_float4(0.5f * (A0.x + B0.x), 0.5f * (A0.y - B0.y),
+                                          0.5f * (A1.x + B1.x), 0.5f * (A1.y - B1.y));
+            const float4 sy = make_float4(0.5f * (A0.y + B0.y), -0.5f * (A0.x - B0.x),
+                                          0.5f * (A1.y + B1.y), -0.5f * (A1.x - B1.x));
+            const float4 sz = make_float4(0.5f * (A2.x + B2.x), 0.5f * (A2.y - B2.y),
+                                          0.5f * (A2.y + B2.y), -0.5f * (A2.x - B2.x));
+            *reinterpret_cast<float4*>(S + (size_t)(0 * H + k) * Dp + j0) = sx;
+            *reinterpret_cast<float4*>(S + (size_t)(1 * H + k) * Dp + j0) = sy;
+            *reinterpret_cast<float4*>(S + (size_t)(2 * H + k) * Dp + j0) = sz;
+        }
+        __syncthreads();
+    };
+
+    // ---- column kx: forward FFT along y, kernel multiply, inverse FFT along y
+    auto column_phase = [&](int b) {
+        const int kx = b * U + u;
+        const bool valid = kx < H;
+        float2* col = S + (size_t)(wave * H + (valid ? kx : 0)) * Dp;
+        float2 v[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int i = t + j * Tf;
+            v[j] = (valid && i < D) ? col[i] : make_float2(0.f, 0.f);
+        }
+        fft_run<P, R, false>(v, mybuf, ltw, t);
+        for (int idx = threadIdx.x; idx < U * P; idx += WG_THREADS) {
+            const int uu = idx / P, ky = idx - uu * P;
+            const int kxx = b * U + uu;
+            if (kxx >= H) continue;
+            const bool lo = ky <= P / 2;
+            const int kq = lo ? ky : P - ky;
+            const float* sp = d.spec + (size_t)kxx * H + kq;
+            const float Kxx = sp[0], Kyy = sp[H * H], Kxy = lo ? sp[2 * H * H] : -sp[2 * H * H],
+                        Kzz = sp[3 * H * H];
+            const float2 mx = BUF(0, uu)[ky], my = BUF(1, uu)[ky], mz = BUF(2, uu)[ky];
+            BUF(0, uu)[ky] = make_float2(Kxx * mx.x + Kxy * my.x, Kxx * mx.y + Kxy * my.y);
+            BUF(1, uu)[ky] = make_float2(Kxy * mx.x + Kyy * my.x, Kxy * mx.y + Kyy * my.y);
+            BUF(2, uu)[ky] = make_float2(Kzz * mz.x, Kzz * mz.y);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < R; ++j) v[j] = mybuf[t + j * Tf];
+        fft_run<P, R, true>(v, mybuf, ltw, t);
+        if (valid)
+            for (int i = t; i < D; i += Tf) col[i] = mybuf[i];
+        __syncthreads();
+    };
+
+    // ---- rebuild the full-length row spectra of a pair and transform back along x
+    auto row_inverse = [&](int b) {
+        for (int idx = threadIdx.x; idx < U * H; idx += WG_THREADS) {
+            const int uu = idx / H, k = idx - uu * H;
+            const int p = b * U + uu;
+            float4 sx = make_float4(0.f, 0.f, 0.f, 0.f), sy = sx, sz = sx;
+            if (p < d.n_pairs) {
+                const int j0 = 2 * p;
+                sx = *reinterpret_cast<const float4*>(S + (size_t)(0 * H + k) * Dp + j0);
+                sy = *reinterpret_cast<const float4*>(S + (size_t)(1 * H + k) * Dp + j0);
+                sz = *reinterpret_cast<const float4*>(S + (size_t)(2 * H + k) * Dp + j0);
+            }
+            // Hx + i Hy of each row, Hz(j0) + i Hz(j1); mirrored half from Hermitian symmetry
+            BUF(0, uu)[k] = make_float2(sx.x - sy.y, sx.y + sy.x);
+            BUF(1, uu)[k] = make_float2(sx.z - sy.w, sx.w + sy.z);
+            BUF(2, uu)[k] = make_float2(sz.x - sz.w, sz.y + sz.z);
+            if (k > 0 && k < P / 2) {
+                const int km = P - k;
+                BUF(0, uu)[km] = make_float2(sx.x + sy.y, sy.x - sx.y);
+                BUF(1, uu)[km] = make_float2(sx.z + sy.w, sy.z - sx.w);
+                BUF(2, uu)[km] = make_float2(sz.x + sz.w, sz.z - sz.y);
+            }
+        }
+        __syncthreads();
+        float2 v[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) v[j] = mybuf[t + j * Tf];
+        fft_run<P, R, true>(v, mybuf, ltw, t);
+    };
+
+    double e_ex = 0.0, e_dm = 0.0, e_ext = 0.0;
+    const float hxf = pr.hx, hyf = pr.hy, hzf = pr.hz, cf = pr.c, al = pr.alpha, dt = pr.dtau;
+
+    // ---- per-cell work after the inverse transforms; new stage state back into LDS
+    // stage s of step n; Ys = state whose field is in LDS; Yn = where the next stage state goes
+    auto cell_update = [&](int b, int s, long long n, const float* Ys, float* Yn) {
+        for (int idx = threadIdx.x; idx < U * D; idx += WG_THREADS) {
+            const int uu = idx / D, i = idx - uu * D;
+            const int p = b * U + uu;
+            if (p >= d.n_pairs) continue;
+            const float2 hz2 = BUF(2, uu)[i];
+            float2 nz2 = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int j = 2 * p + r;
+                if (j >= D) break;
+                const float2 hxy = BUF(r, uu)[i];
+                const float Hx = hxy.x, Hy = hxy.y, Hz = r == 0 ? hz2.x : hz2.y;
+                const int cell = j * D + i;
+                float nx = 0.f, ny = 0.f, nzv = 0.f;
+                if (mask[cell]) {
+                    const float mx = Ys[cell], my = Ys[DD + cell], mz = Ys[2 * DD + cell];
+                    float ex = 0.f, ey = 0.f, ez = 0.f;
+                    double exd = 0.0, eyd = 0.0, ezd = 0.0;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int jj = j + (q == 0 ? -1 : q == 1 ? 1 : 0);
+                        const int ii = i + (q == 2 ? -1 : q == 3 ? 1 : 0);
+                        if (jj < 0 || jj >= D || ii < 0 || ii >= D) continue;
+                        const int cn = jj * D + ii;
+                        if (!mask[cn]) continue;
+                        const float vx = Ys[cn], vy = Ys[DD + cn], vz = Ys[2 * DD + cn];
+                        if (mode == MODE_ENERGY) {
+                            exd += vx;
+                            eyd += vy;
+                            ezd += vz;
+                        } else {
+                            ex += vx;
+                            ey += vy;
+                            ez += vz;
+                        }
+                    }
+                    if (mode == MODE_DEMAG) {
+                        out[cell] = Hx;
+                        out[DD + cell] = Hy;
+                        out[2 * DD + cell] = Hz;
+                        continue;
+                    }
+                    if (mode == MODE_ENERGY) {
+                        const double mxd = mx, myd = my, mzd = mz;
+                        e_ex += -0.5 * (mxd * exd + myd * eyd + mzd * ezd);
+                        e_dm += -0.5 * pr.c_d * (mxd * (double)Hx + myd * (double)Hy + mzd * (double)Hz);
+                        e_ext += -pr.c_d * (mxd * pr.hx_d + myd * pr.hy_d + mzd * pr.hz_d);
+                        continue;
+                    }
+                    const float bx = ex + cf * (hxf + Hx);
+                    const float by = ey + cf * (hyf + Hy);
+                    const float bz = ez + cf * (hzf + Hz);
+                    if (mode == MODE_RHS || mode == MODE_RK4) {
+                        // f = m x b - alpha m x (m x b)
+                        const float px = my * bz - mz * by, py = mz * bx - mx * bz, pz = mx * by - my * bx;
+                        const float fx = px - al * (my * pz - mz * py);
+                        const float fy = py - al * (mz * px - mx * pz);
+                        const float fz = pz - al * (mx * py - my * px);
+                        if (mode == MODE_RHS) {
+                            out[cell] = fx;
+                            out[DD + cell] = fy;
+                            out[2 * DD + cell] = fz;
+                            continue;
+                        }
+                        const float y0x = m[cell], y0y = m[DD + cell], y0z = m[2 * DD + cell];
+                        if (s == 0) {
+                            d.acc[cell] = fx;
+                            d.acc[DD + cell] = fy;
+                            d.acc[2 * DD + cell] = fz;
+                        } else if (s < 3) {
+                            d.acc[cell] += 2.f * fx;
+                            d.acc[DD + cell] += 2.f * fy;
+                            d.acc[2 * DD + cell] += 2.f * fz;
+                        }
+                        if (s < 3) {
+                            const float h = (s == 2) ? dt : 0.5f * dt;
+                            nx = y0x + h * fx;
+                            ny = y0y + h * fy;
+                            nzv = y0z + h * fz;
+                        } else {
+                            const float h6 = dt * (1.0f / 6.0f);
+                            nx = y0x + h6 * (d.acc[cell] + fx);
+                            ny = y0y + h6 * (d.acc[DD + cell] + fy);
+                            nzv = y0z + h6 * (d.acc[2 * DD + cell] + fz);
+                            if (pr.renorm) {
+                                const float rn = 1.0f / sqrtf(nx * nx + ny * ny + nzv * nzv);
+                                nx *= rn;
+                                ny *= rn;
+                                nzv *= rn;
+                            }
+                            if (!(isfinite(nx) && isfinite(ny) && isfinite(nzv)))
+                                __hip_atomic_fetch_or(a.err, (int)ERR_NONFINITE, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                    } else {  // MODE_HEUN
+                        const float3 w = thermal_normals(a.seed, a.step0 + (unsigned long long)n,
+                                                         (unsigned long long)cell,
+                                                         (unsigned long long)(a.replica0 + d.k));
+                        const float sg = pr.sigma;
+                        const float gx = bx * dt + sg * w.x, gy = by * dt + sg * w.y, gz = bz * dt + sg * w.z;
+                        const float px = my * gz - mz * gy, py = mz * gx - mx * gz, pz = mx * gy - my * gx;
+                        const float dx = px - al * (my * pz - mz * py);
+                        const float dy = py - al * (mz * px - mx * pz);
+                        const float dz = pz - al * (mx * py - my * px);
+                        if (s == 0) {
+                            d.acc[cell] = dx;
+                            d.acc[DD + cell] = dy;
+                            d.acc[2 * DD + cell] = dz;
+                            nx = mx + dx;
+                            ny = my + dy;
+                            nzv = mz + dz;
+                        } else {
+                            nx = m[cell] + 0.5f * (d.acc[cell] + dx);
+                            ny = m[DD + cell] + 0.5f * (d.acc[DD + cell] + dy);
+                            nzv = m[2 * DD + cell] + 0.5f * (d.acc[2 * DD + cell] + dz);
+                            if (pr.renorm) {
+                                const float rn = 1.0f / sqrtf(nx * nx + ny * ny + nzv * nzv);
+                                nx *= rn;
+                                ny *= rn;
+                                nzv *= rn;
+                            }
+                            if (!(isfinite(nx) && isfinite(ny) && isfinite(nzv)))
+                                __hip_atomic_fetch_or(a.err, (int)ERR_NONFINITE, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                    }
+                } else if (mode == MODE_DEMAG || mode == MODE_RHS) {
+                    out[cell] = 0.f;
+                    out[DD + cell] = 0.f;
+                    out[2 * DD + cell] = 0.f;
+                    continue;
+                } else if (mode == MODE_ENERGY) {
+                    continue;
+                }
+                // integrators: store the next stage state (zero outside the disk)
+                Yn[cell] = nx;
+                Yn[DD + cell] = ny;
+                Yn[2 * DD + cell] = nzv;
+                BUF(r, uu)[i] = make_float2(nx, ny);
+                if (r == 0) nz2.x = nzv; else nz2.y = nzv;
+            }
+            if (mode == MODE_RK4 || mode == MODE_HEUN) BUF(2, uu)[i] = nz2;
+        }
+        __syncthreads();
+    };
+
+    // ---------------------------------------------------------------- program
+    for (int b = g; b < n_rb; b += G) {
+        load_state_rows(b, m);
+        row_forward_store(b);
+    }
+    if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
+
+    if (mode == MODE_DEMAG || mode == MODE_RHS || mode == MODE_ENERGY) {
+        for (int b = g; b < n_cb; b += G) column_phase(b);
+        if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
+        for (int b = g; b < n_rb; b += G) {
+            row_inverse(b);
+            cell_update(b, 0, 0, m, nullptr);
+        }
+        if (mode == MODE_ENERGY) {
+            __shared__ double red[3][3];
+            const double s0 = wave_sum(e_ex), s1 = wave_sum(e_dm), s2 = wave_sum(e_ext);
+            if (lane == 0) {
+                red[wave][0] = s0;
+                red[wave][1] = s1;
+                red[wave][2] = s2;
+            }
+            __syncthreads();
+            if (threadIdx.x < 3) {
+                const int q = threadIdx.x;
+                d.part[g * 4 + q] = red[0][q] + red[1][q] + red[2][q];
+            }
+        }
+        return;
+    }
+
+    const int nst = (mode == MODE_RK4) ? 4 : 2;
+    for (long long n = 0; n < a.nsteps; ++n) {
+        for (int s = 0; s < nst; ++s) {
+            for (int b = g; b < n_cb; b += G) column_phase(b);
+            if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
+            const bool last = (n == a.nsteps - 1) && (s == nst - 1);
+            const float* Ys;
+            float* Yn;
+            if (nst == 4) {
+                Ys = (s == 0) ? m : (s == 2) ? d.yb : d.ya;
+                Yn = (s == 3) ? m : (s == 1) ? d.yb : d.ya;
+            } else {
+                Ys = (s == 0) ? m : d.ya;
+                Yn = (s == 0) ? d.ya : m;
+            }
+            for (int b = g; b < n_rb; b += G) {
+                row_inverse(b);
+                cell_update(b, s, n, Ys, Yn);
+                if (!last) row_forward_store(b);
+            }
+            if (!last && !group_barrier(d.bar, ++epoch * G, G, a.err)) return;
+        }
+    }
+#undef BUF
+}
+
+__global__ __launch_bounds__(WG_THREADS) void llg_persistent(KArgs a) {
+    __shared__ float2 lds[LDS_FFT];
+    __shared__ float2 ltw[MAX_P];
+    const int wg = blockIdx.x;
+    const int di = a.wg2disk[wg];
+    if (di < 0) return;
+    const int g = a.wg2local[wg];
+    const DiskDesc d = a.disks[di];
+    const DiskPrm pr = a.prm[di];
+    switch (d.P) {
+        case 64: run_disk<64, 4>(a, d, pr, g, lds, ltw); break;
+        case 128: run_disk<128, 4>(a, d, pr, g, lds, ltw); break;
+        case 256: run_disk<256, 4>(a, d, pr, g, lds, ltw); break;
+        case 512: run_disk<512, 8>(a, d, pr, g, lds, ltw); break;
+        default: break;
+    }
+}
+
+__global__ void zero_u32(unsigned int* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// E = E_ex + E_demag + E_ext per disk from the per-workgroup partials, summed in
+// workgroup order (deterministic).
+__global__ void energy_finalize(const DiskDesc* disks, int n, double* out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const DiskDesc d = disks[k];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int g = 0; g < d.G; ++g) {
+        s0 += d.part[g * 4 + 0];
+        s1 += d.part[g * 4 + 1];
+        s2 += d.part[g * 4 + 2];
+    }
+    out[4 * k + 0] = s0 + s1 + s2;
+    out[4 * k + 1] = s0;
+    out[4 * k + 2] = s1;
+    out[4 * k + 3] = s2;
+}
+
+// Noise field of one Heun step (test hook), packed like the state.
+__global__ void noise_kernel(const DiskDesc* disks, int n, float* w, unsigned long long seed,
+                             unsigned long long step, unsigned int replica0) {
+    const int k = blockIdx.y;
+    if (k >= n) return;
+    const DiskDesc d = disks[k];
+    const int DD = d.D * d.D;
+    float* out = w + d.m_off;
+    for (int cell = blockIdx.x * blockDim.x + threadIdx.x; cell < DD; cell += gridDim.x * blockDim.x) {
+        float3 v = make_float3(0.f, 0.f, 0.f);
+        if (d.mask[cell]) v = thermal_normals(seed, step, (unsigned long long)cell, (unsigned long long)(replica0 + d.k));
+        out[cell] = v.x;
+        out[DD + cell] = v.y;
+        out[2 * DD + cell] = v.z;
+    }
+}
+
+constexpr int OBS_THREADS = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < OBS_THREADS / 64; ++w) s += sh[w];
+    return s;
+}
+
+// <m> per disk, float64.
+__global__ __launch_bounds__(OBS_THREADS) void mean_kernel(const DiskDesc* disks, const float* m_base, double* out) {
+    __shared__ double sh[OBS_THREADS / 64];
+    const DiskDesc d = disks[blockIdx.x];
+    const int DD = d.D * d.D;
+    const float* m = m_base + d.m_off;
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int c = threadIdx.x; c < DD; c += OBS_THREADS)
+        if (d.mask[c]) {
+            sx += m[c];
+            sy += m[DD + c];
+            sz += m[2 * DD + c];
+        }
+    sx = block_sum(sx, sh);
+    sy = block_sum(sy, sh);
+    sz = block_sum(sz, sh);
+    if (threadIdx.x == 0) {
+        out[3 * blockIdx.x + 0] = sx / d.n_cells;
+        out[3 * blockIdx.x + 1] = sy / d.n_cells;
+        out[3 * blockIdx.x + 2] = sz / d.n_cells;
+    }
+}
+
+__device__ __forceinline__ double wrap_pi(double x) {
+    // x + pi reduced into [0, 2 pi), minus pi
+    const double two_pi = 6.283185307179586476925286766559;
+    const double pi = 3.1415926535897932384626433832795;
+    double t = fmod(x + pi, two_pi);
+    if (t < 0.0) t += two_pi;
+    return t - pi;
+}
+
+// Vortex core position per disk, float64 (one workgroup per disk).
+// hint: per disk (x, y) in nm, NaN = no hint.
+__global__ __launch_bounds__(OBS_THREADS) void core_kernel(const DiskDesc* disks, const float* m_base,
+                                                           const double* hint, double a_nm, double cutoff_cells,
+                                                           double* out) {
+    __shared__ double sh[OBS_THREADS / 64];
+    __shared__ double s_score[OBS_THREADS / 64];
+    __shared__ int s_idx[OBS_THREADS / 64];
+    const int k = blockIdx.x;
+    const DiskDesc d = disks[k];
+    const int D = d.D, DD = D * D, Dm = D - 1;
+    const float* m = m_base + d.m_off;
+    const unsigned char* mask = d.mask;
+    const double half = (D - 1) / 2.0;
+    const double two_pi = 6.283185307179586476925286766559;
+    const double hx = hint[2 * k], hy = hint[2 * k + 1];
+    const bool use_hint = !(isnan(hx) || isnan(hy));
+
+    double best = -INFINITY;
+    int best_idx = 0x7fffffff;
+    int nplus = 0;
+    for (int p = threadIdx.x; p < Dm * Dm; p += OBS_THREADS) {
+        const int j = p / Dm, i = p - j * Dm;
+        const int ca = j * D + i, cb = ca + 1, cc = ca + D + 1, cd = ca + D;
+        if (!(mask[ca] && mask[cb] && mask[cc] && mask[cd])) continue;
+        const double fa = atan2((double)m[DD + ca], (double)m[ca]);
+        const double fb = atan2((double)m[DD + cb], (double)m[cb]);
+        const double fc = atan2((double)m[DD + cc], (double)m[cc]);
+        const double fd = atan2((double)m[DD + cd], (double)m[cd]);
+        const double s = wrap_pi(fb - fa) + wrap_pi(fc - fb) + wrap_pi(fd - fc) + wrap_pi(fa - fd);
+        if ((int)rint(s / two_pi) != 1) continue;
+        ++nplus;
+        double score;
+        const double cx = ((double)i - half) + 0.5, cy = ((double)j - half) + 0.5;
+        if (use_hint) {
+            const double ddx = cx - hx / a_nm, ddy = cy - hy / a_nm;
+            score = -(ddx * ddx + ddy * ddy);
+        } else {
+            const double za = m[2 * DD + ca], zb = m[2 * DD + cb], zc = m[2 * DD + cc], zd = m[2 * DD + cd];
+            score = za * za + zb * zb + zc * zc + zd * zd;
+        }
+        if (score > best || (score == best && p < best_idx)) {
+            best = score;
+            best_idx = p;
+        }
+    }
+    // argmax (higher score, then lower index) over the workgroup
+    for (int o = 32; o > 0; o >>= 1) {
+        const double os = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(best_idx, o, 64);
+        if (os > best || (os == best && oi < best_idx)) {
+            best = os;
+            best_idx = oi;
+        }
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
+        s_score[wave] = best;
+        s_idx[wave] = best_idx;
+    }
+    const double np = block_sum((double)nplus, sh);
+    double bs = s_score[0];
+    int bi = s_idx[0];
+    for (int w = 1; w < OBS_THREADS / 64; ++w)
+        if (s_score[w] > bs || (s_score[w] == bs && s_idx[w] < bi)) {
+            bs = s_score[w];
+            bi = s_idx[w];
+        }
+    const bool found = np > 0.5;
+    double xv = NAN, yv = NAN;
+    if (found) {
+        const int j = bi / Dm, i = bi - j * Dm;
+        xv = ((double)i - half) + 0.5;
+        yv = ((double)j - half) + 0.5;
+    }
+    const double c2 = cutoff_cells * cutoff_cells;
+    double sw = 0.0, swx = 0.0, swy = 0.0;
+    for (int c = threadIdx.x; c < DD; c += OBS_THREADS) {
+        if (!mask[c]) continue;
+        const int j = c / D, i = c - j * D;
+        const double x = (double)i - half, y = (double)j - half;
+        if (found) {
+            const double ddx = x - xv, ddy = y - yv;
+            if (!(ddx * ddx + ddy * ddy < c2)) continue;
+        }
+        const double z = m[2 * DD + c];
+        const double w = z * z;
+        sw += w;
+        swx += w * x;
+        swy += w * y;
+    }
+    sw = block_sum(sw, sh);
+    swx = block_sum(swx, sh);
+    swy = block_sum(swy, sh);
+    if (threadIdx.x == 0) {
+        out[5 * k + 0] = swx / sw * a_nm;
+        out[5 * k + 1] = swy / sw * a_nm;
+        out[5 * k + 2] = xv * a_nm;
+        out[5 * k + 3] = yv * a_nm;
+        out[5 * k + 4] = np;
+    }
+}
+
+}  // namespace llg

@@ -1,0 +1,645 @@
+// lib_llgdisk: host side of the C ABI declared in include/llgdisk.h.
+//
+// Owns geometry set-up (mask, thin-film kernel spectra in float64, twiddle
+// tables), workspaces, the workgroup-to-disk map of the persistent launch and
+// the parameter staging.  Every step of the hot path runs in the kernels of
+// llg_kernels.hpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/llgdisk.h"
+#include "llg_kernels.hpp"
+
+using namespace llg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(LLG_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));        \
+    } while (0)
+
+// ------------------------------------------------------------------ geometry
+// Thin-film kernels of Sec. II.B at displacement (u, v) in units of a, ell = L/a.
+void green(double u, double v, double ell, double* kxx, double* kyy, double* kxy, double* kzz) {
+    const double r2 = u * u + v * v;
+    if (r2 == 0.0) {
+        const double ro = 1.0 / std::sqrt(M_PI);
+        const double so = std::sqrt(ell * ell + ro * ro);
+        const double nz = (ell + ro - so) / ell;
+        const double nx = (so - ro) / (2.0 * ell);
+        *kxx = -nx;
+        *kyy = -nx;
+        *kxy = 0.0;
+        *kzz = -nz;
+        return;
+    }
+    const double r = std::sqrt(r2), s = std::sqrt(r2 + ell * ell);
+    const double pre = ell / (2.0 * M_PI * r2 * r2);
+    *kxx = pre * (u * u / s - v * v / (s + r));
+    *kyy = pre * (v * v / s - u * u / (s + r));
+    *kxy = pre * ((2.0 * s + r) / (s + r)) * (u * v / s);
+    *kzz = -ell / (2.0 * M_PI * r * s * (s + r));
+}
+
+// In-place radix-2 complex FFT (forward, e^{-i}), float64, host.
+void fft1d(std::complex<double>* x, int n, int stride) {
+    for (int i = 1, j = 0; i < n; ++i) {
+        int bit = n >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) std::swap(x[(size_t)i * stride], x[(size_t)j * stride]);
+    }
+    for (int len = 2; len <= n; len <<= 1) {
+        const double ang = -2.0 * M_PI / len;
+        for (int i = 0; i < n; i += len)
+            for (int k = 0; k < len / 2; ++k) {
+                const std::complex<double> w(std::cos(ang * k), std::sin(ang * k));
+                std::complex<double>& a = x[(size_t)(i + k) * stride];
+                std::complex<double>& b = x[(size_t)(i + k + len / 2) * stride];
+                const std::complex<double> t = w * b;
+                b = a - t;
+                a = a + t;
+            }
+    }
+}
+
+struct Geom {
+    int D, P, n_cells;
+    double ell;
+    float* spec = nullptr;           // device [4][H][H]
+    unsigned char* mask = nullptr;   // device [D][D]
+};
+
+// Quarter-plane real spectra / P^2 of the four wrapped kernels, [4][H][H].
+std::vector<float> kernel_spectra(int D, int P, double ell) {
+    const int H = P / 2 + 1;
+    std::vector<float> out((size_t)4 * H * H);
+    std::vector<std::complex<double>> w((size_t)P * P);
+    for (int q = 0; q < 4; ++q) {
+        std::fill(w.begin(), w.end(), std::complex<double>(0.0, 0.0));
+        for (int v = -(D - 1); v <= D - 1; ++v)
+            for (int u = -(D - 1); u <= D - 1; ++u) {
+                double k[4];
+                green(u, v, ell, &k[0], &k[1], &k[2], &k[3]);
+                w[(size_t)((v + P) % P) * P + ((u + P) % P)] = k[q];
+            }
+        for (int row = 0; row < P; ++row) fft1d(&w[(size_t)row * P], P, 1);
+        for (int col = 0; col < P; ++col) fft1d(&w[col], P, P);
+        const double inv = 1.0 / ((double)P * P);
+        for (int kx = 0; kx < H; ++kx)
+            for (int ky = 0; ky < H; ++ky)
+                out[((size_t)q * H + kx) * H + ky] = (float)(w[(size_t)ky * P + kx].real() * inv);
+    }
+    return out;
+}
+
+std::vector<unsigned char> disk_mask(int D, int* n_cells) {
+    std::vector<unsigned char> m((size_t)D * D);
+    const double c = (D - 1) / 2.0, r2 = (D / 2.0) * (D / 2.0);
+    int n = 0;
+    for (int j = 0; j < D; ++j)
+        for (int i = 0; i < D; ++i) {
+            const double x = i - c, y = j - c;
+            const bool in = x * x + y * y <= r2;
+            m[(size_t)j * D + i] = in;
+            n += in;
+        }
+    *n_cells = n;
+    return m;
+}
+
+int radix_for(int P) { return P == 512 ? 8 : 4; }
+
+}  // namespace
+
+struct llg_disk_s {
+    int device = 0;
+    int n = 0;
+    double a_nm = 2.0;
+    std::vector<int> D, P, n_cells, G;
+    std::vector<double> R_nm, L_nm;
+    std::vector<long long> m_off;
+    long long state_size = 0;
+    std::vector<Geom> geoms;
+    std::vector<int> geom_of;
+    std::map<int, float2*> twiddles;
+    std::vector<void*> allocs;
+    DiskDesc* desc_dev = nullptr;
+    DiskPrm* prm_dev = nullptr;
+    DiskPrm* prm_pin = nullptr;
+    std::vector<DiskPrm> prm_cache;
+    bool prm_valid = false;
+    hipEvent_t prm_event = nullptr;
+    double* hint_dev = nullptr;
+    double* hint_pin = nullptr;
+    hipEvent_t hint_event = nullptr;
+    int* wg2disk = nullptr;
+    int* wg2local = nullptr;
+    int n_wg = 0;
+    unsigned int* bars = nullptr;
+    int n_bars = 0;
+    int* err_dev = nullptr;
+
+    ~llg_disk_s() {
+        for (void* p : allocs) (void)hipFree(p);
+        if (prm_pin) (void)hipHostFree(prm_pin);
+        if (hint_pin) (void)hipHostFree(hint_pin);
+        if (prm_event) (void)hipEventDestroy(prm_event);
+        if (hint_event) (void)hipEventDestroy(hint_event);
+    }
+    template <typename T>
+    int dalloc(T** p, size_t count) {
+        void* q = nullptr;
+        hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+        if (e != hipSuccess) return fail(LLG_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        allocs.push_back(q);
+        *p = static_cast<T*>(q);
+        return 0;
+    }
+};
+
+namespace {
+
+int max_coresident_workgroups(int* out) {
+    int dev = 0, ncu = 0, per_cu = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(llg_persistent),
+                                                         WG_THREADS, 0));
+    *out = ncu * per_cu;
+    return 0;
+}
+
+int choose_P(int D, int P_override, int* P) {
+    const int need = 2 * D - 1;
+    if (P_override == 0) {
+        int p = 64;
+        while (p < 2 * D) p *= 2;
+        *P = p;
+    } else {
+        *P = P_override;
+    }
+    if (*P != 64 && *P != 128 && *P != 256 && *P != 512)
+        return fail(LLG_EUNSUPPORTED, "FFT size " + std::to_string(*P) + " unsupported (64, 128, 256 or 512; disks up to D = 256)");
+    if (*P < need) return fail(LLG_EINVAL, "P = " + std::to_string(*P) + " < 2D-1 = " + std::to_string(need));
+    return 0;
+}
+
+int create(int n, const double* R_nm, const double* L_nm, double a_nm, const int* wg_per_disk,
+           const int* P_override, llg_disk* out) {
+    if (!out) return fail(LLG_EINVAL, "null output handle");
+    *out = nullptr;
+    if (n <= 0 || !R_nm || !L_nm) return fail(LLG_EINVAL, "need n >= 1 disks");
+    if (!(a_nm > 0)) return fail(LLG_EINVAL, "cell edge must be positive");
+    auto h = new llg_disk_s();
+    auto bail = [&](int rc) {
+        delete h;
+        return rc;
+    };
+    HIP_TRY(hipGetDevice(&h->device));
+    h->n = n;
+    h->a_nm = a_nm;
+    std::map<std::tuple<int, int, long long>, int> geom_index;
+    for (int k = 0; k < n; ++k) {
+        const double dd = 2.0 * R_nm[k] / a_nm;
+        const int D = (int)std::lround(dd);
+        if (!(std::fabs(dd - D) <= 1e-9) || D < 1)
+            return bail(fail(LLG_EINVAL, "disk " + std::to_string(k) + ": 2R/a is not a positive integer"));
+        if (!(L_nm[k] > 0)) return bail(fail(LLG_EINVAL, "disk " + std::to_string(k) + ": thickness must be positive"));
+        int P = 0;
+        int rc = choose_P(D, P_override ? P_override[k] : 0, &P);
+        if (rc) return bail(rc);
+        const double ell = L_nm[k] / a_nm;
+        const auto key = std::make_tuple(D, P, (long long)std::llround(ell * 1e12));
+        auto it = geom_index.find(key);
+        int gi;
+        if (it == geom_index.end()) {
+            Geom g;
+            g.D = D;
+            g.P = P;
+            g.ell = ell;
+            std::vector<unsigned char> mk = disk_mask(D, &g.n_cells);
+            std::vector<float> sp = kernel_spectra(D, P, ell);
+            if ((rc = h->dalloc(&g.mask, mk.size()))) return bail(rc);
+            if ((rc = h->dalloc(&g.spec, sp.size()))) return bail(rc);
+            HIP_TRY(hipMemcpy(g.mask, mk.data(), mk.size(), hipMemcpyHostToDevice));
+            HIP_TRY(hipMemcpy(g.spec, sp.data(), sp.size() * sizeof(float), hipMemcpyHostToDevice));
+            gi = (int)h->geoms.size();
+            h->geoms.push_back(g);
+            geom_index[key] = gi;
+        } else {
+            gi = it->second;
+        }
+        if (!h->twiddles.count(P)) {
+            std::vector<float2> tw(P);
+            for (int e = 0; e < P; ++e)
+                tw[e] = make_float2((float)std::cos(2.0 * M_PI * e / P), (float)(-std::sin(2.0 * M_PI * e / P)));
+            float2* tdev = nullptr;
+            if ((rc = h->dalloc(&tdev, P))) return bail(rc);
+            HIP_TRY(hipMemcpy(tdev, tw.data(), P * sizeof(float2), hipMemcpyHostToDevice));
+            h->twiddles[P] = tdev;
+        }
+        h->geom_of.push_back(gi);
+        h->D.push_back(D);
+        h->P.push_back(P);
+        h->n_cells.push_back(h->geoms[gi].n_cells);
+        h->R_nm.push_back(R_nm[k]);
+        h->L_nm.push_back(L_nm[k]);
+        h->m_off.push_back(h->state_size);
+        h->state_size += 3LL * D * D;
+    }
+
+    // ---- workgroups per disk
+    int cap = 0;
+    int rc = max_coresident_workgroups(&cap);
+    if (rc) return bail(rc);
+    std::vector<int> useful(n), G(n);
+    std::vector<double> work(n);
+    for (int k = 0; k < n; ++k) {
+        const int P = h->P[k], D = h->D[k];
+        const int U = 64 / (P / radix_for(P));
+        const int H = P / 2 + 1;
+        const int n_pairs = (D + 1) / 2;
+        useful[k] = std::max((n_pairs + U - 1) / U, (H + U - 1) / U);
+        work[k] = (double)((n_pairs + U - 1) / U + (H + U - 1) / U) * P * std::log2((double)P);
+    }
+    if (wg_per_disk) {
+        for (int k = 0; k < n; ++k) {
+            if (wg_per_disk[k] < 1) return bail(fail(LLG_EINVAL, "wg_per_disk must be >= 1"));
+            G[k] = std::min(wg_per_disk[k], useful[k]);
+        }
+    } else {
+        const double wsum = std::accumulate(work.begin(), work.end(), 0.0);
+        for (int k = 0; k < n; ++k)
+            G[k] = std::max(1, std::min(useful[k], (int)std::floor(cap * work[k] / wsum)));
+    }
+    long long total = std::accumulate(G.begin(), G.end(), 0LL);
+    while (total > cap) {  // trim the disks with the most workgroups
+        int kmax = (int)(std::max_element(G.begin(), G.end()) - G.begin());
+        if (G[kmax] <= 1) break;
+        --G[kmax];
+        --total;
+    }
+    if (total > cap)
+        return bail(fail(LLG_EUNSUPPORTED, "batch needs " + std::to_string(total) + " workgroups but only " +
+                                               std::to_string(cap) + " can be co-resident"));
+    h->G = G;
+
+    // ---- workgroup map: disks whose workgroups fit one XCD stay on one XCD
+    // (workgroup w is dispatched to XCD w mod 8); larger disks take consecutive ids.
+    constexpr int NXCD = 8;
+    std::vector<int> w2d, w2l;
+    {
+        std::vector<std::vector<std::pair<int, int>>> lanes(NXCD);  // per XCD: (disk, local)
+        std::vector<long long> load(NXCD, 0);
+        std::vector<int> big;
+        std::vector<int> order(n);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return G[x] > G[y]; });
+        for (int k : order) {
+            if (n > 1 && G[k] * NXCD <= cap) {
+                const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                for (int l = 0; l < G[k]; ++l) lanes[x].push_back({k, l});
+                load[x] += G[k];
+            } else {
+                big.push_back(k);
+            }
+        }
+        for (int k : big)
+            for (int l = 0; l < G[k]; ++l) {
+                w2d.push_back(k);
+                w2l.push_back(l);
+            }
+        const int base = (int)w2d.size();
+        const int pad = (NXCD - base % NXCD) % NXCD;
+        for (int i = 0; i < pad; ++i) {
+            w2d.push_back(-1);
+            w2l.push_back(0);
+        }
+        size_t depth = 0;
+        for (auto& l : lanes) depth = std::max(depth, l.size());
+        const size_t start = w2d.size();
+        for (size_t s = 0; s < depth; ++s)
+            for (int x = 0; x < NXCD; ++x) {
+                // id = start + s*8 + x, and start is a multiple of 8, so id mod 8 == x
+                if (s < lanes[x].size()) {
+                    w2d.push_back(lanes[x][s].first);
+                    w2l.push_back(lanes[x][s].second);
+                } else {
+                    w2d.push_back(-1);
+                    w2l.push_back(0);
+                }
+            }
+        (void)start;
+        while (!w2d.empty() && w2d.back() < 0) {
+            w2d.pop_back();
+            w2l.pop_back();
+        }
+    }
+    if ((int)w2d.size() > cap) {
+        // the padded layout does not fit: fall back to consecutive ids
+        w2d.clear();
+        w2l.clear();
+        for (int k = 0; k < n; ++k)
+            for (int l = 0; l < G[k]; ++l) {
+                w2d.push_back(k);
+                w2l.push_back(l);
+            }
+    }
+    h->n_wg = (int)w2d.size();
+    if ((rc = h->dalloc(&h->wg2disk, w2d.size()))) return bail(rc);
+    if ((rc = h->dalloc(&h->wg2local, w2l.size()))) return bail(rc);
+    HIP_TRY(hipMemcpy(h->wg2disk, w2d.data(), w2d.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(h->wg2local, w2l.data(), w2l.size() * sizeof(int), hipMemcpyHostToDevice));
+
+    // ---- workspaces and descriptors
+    h->n_bars = n * 32;  // one 128-byte line per disk
+    if ((rc = h->dalloc(&h->bars, h->n_bars))) return bail(rc);
+    if ((rc = h->dalloc(&h->err_dev, 1))) return bail(rc);
+    HIP_TRY(hipMemset(h->err_dev, 0, sizeof(int)));
+    std::vector<DiskDesc> desc(n);
+    for (int k = 0; k < n; ++k) {
+        DiskDesc& d = desc[k];
+        const Geom& g = h->geoms[h->geom_of[k]];
+        d.D = h->D[k];
+        d.P = h->P[k];
+        d.H = d.P / 2 + 1;
+        d.Dp = d.D + (d.D & 1);
+        d.n_pairs = (d.D + 1) / 2;
+        d.G = G[k];
+        d.n_cells = g.n_cells;
+        d.k = k;
+        d.m_off = h->m_off[k];
+        const size_t DD = (size_t)d.D * d.D;
+        if ((rc = h->dalloc(&d.ya, 3 * DD))) return bail(rc);
+        if ((rc = h->dalloc(&d.yb, 3 * DD))) return bail(rc);
+        if ((rc = h->dalloc(&d.acc, 3 * DD))) return bail(rc);
+        if ((rc = h->dalloc(&d.S, (size_t)3 * d.H * d.Dp))) return bail(rc);
+        HIP_TRY(hipMemset(d.S, 0, (size_t)3 * d.H * d.Dp * sizeof(float2)));
+        if ((rc = h->dalloc(&d.part, (size_t)4 * d.G))) return bail(rc);
+        d.spec = g.spec;
+        d.mask = g.mask;
+        d.tw = h->twiddles[d.P];
+        d.bar = h->bars + 32 * k;
+    }
+    if ((rc = h->dalloc(&h->desc_dev, n))) return bail(rc);
+    HIP_TRY(hipMemcpy(h->desc_dev, desc.data(), n * sizeof(DiskDesc), hipMemcpyHostToDevice));
+    if ((rc = h->dalloc(&h->prm_dev, n))) return bail(rc);
+    if ((rc = h->dalloc(&h->hint_dev, 2 * (size_t)n))) return bail(rc);
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->prm_pin), n * sizeof(DiskPrm), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->hint_pin), 2 * n * sizeof(double), hipHostMallocDefault));
+    HIP_TRY(hipEventCreateWithFlags(&h->prm_event, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&h->hint_event, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(h->prm_event, 0));
+    HIP_TRY(hipEventRecord(h->hint_event, 0));
+    h->prm_cache.resize(n);
+    HIP_TRY(hipDeviceSynchronize());
+    *out = h;
+    return 0;
+}
+
+int upload_params(llg_disk h, const llg_params* p, hipStream_t st) {
+    if (!p) return fail(LLG_EINVAL, "null params");
+    std::vector<DiskPrm> v(h->n);
+    for (int k = 0; k < h->n; ++k) {
+        const llg_params& q = p[k];
+        if (!(q.dtau >= 0) || !(q.alpha >= 0) || !(q.temp >= 0) || !std::isfinite(q.c))
+            return fail(LLG_EINVAL, "invalid parameters for disk " + std::to_string(k));
+        DiskPrm& d = v[k];
+        d.alpha = (float)q.alpha;
+        d.c = (float)q.c;
+        d.hx = (float)q.hext[0];
+        d.hy = (float)q.hext[1];
+        d.hz = (float)q.hext[2];
+        d.dtau = (float)q.dtau;
+        double var = 2.0 * q.alpha * q.temp * q.dtau;
+        if (q.fd_factor) var /= 1.0 + q.alpha * q.alpha;
+        d.sigma = (float)std::sqrt(var);
+        d.renorm = q.renorm ? 1 : 0;
+        d.c_d = q.c;
+        d.hx_d = q.hext[0];
+        d.hy_d = q.hext[1];
+        d.hz_d = q.hext[2];
+    }
+    if (h->prm_valid && std::memcmp(v.data(), h->prm_cache.data(), v.size() * sizeof(DiskPrm)) == 0) return 0;
+    HIP_TRY(hipEventSynchronize(h->prm_event));  // the staging buffer is free again
+    std::memcpy(h->prm_pin, v.data(), v.size() * sizeof(DiskPrm));
+    HIP_TRY(hipMemcpyAsync(h->prm_dev, h->prm_pin, v.size() * sizeof(DiskPrm), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(h->prm_event, st));
+    h->prm_cache = v;
+    h->prm_valid = true;
+    return 0;
+}
+
+int launch(llg_disk h, int mode, float* m, float* out, long long nsteps, unsigned long long seed,
+           unsigned long long step0, unsigned int replica0, hipStream_t st) {
+    const int nb = (h->n_bars + 255) / 256;
+    hipLaunchKernelGGL(zero_u32, dim3(nb), dim3(256), 0, st, h->bars, h->n_bars);
+    HIP_TRY(hipGetLastError());
+    KArgs a;
+    a.disks = h->desc_dev;
+    a.prm = h->prm_dev;
+    a.wg2disk = h->wg2disk;
+    a.wg2local = h->wg2local;
+    a.m = m;
+    a.out = out;
+    a.nsteps = nsteps;
+    a.seed = seed;
+    a.step0 = step0;
+    a.replica0 = replica0;
+    a.mode = mode;
+    a.err = h->err_dev;
+    void* args[] = {&a};
+    HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(llg_persistent), dim3(h->n_wg),
+                                       dim3(WG_THREADS), args, 0, st));
+    return 0;
+}
+
+int check_handle(llg_disk h) {
+    if (!h) return fail(LLG_EINVAL, "null handle");
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != h->device) return fail(LLG_EINVAL, "handle belongs to device " + std::to_string(h->device));
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int llg_params_from_si(double A, double Ms, double gamma, double a_nm, double L_nm, double dt_ps, double T_K,
+                       double alpha, llg_params* out, double* lambda_ex_nm) {
+    if (!out) return fail(LLG_EINVAL, "null output");
+    if (!(A > 0 && Ms > 0 && gamma > 0 && a_nm > 0 && L_nm > 0 && dt_ps >= 0 && T_K >= 0 && alpha >= 0))
+        return fail(LLG_EINVAL, "material and grid parameters must be positive");
+    const double mu0 = 4e-7 * M_PI, kB = 1.380649e-23;
+    const double a = a_nm * 1e-9, L = L_nm * 1e-9;
+    const double lam = std::sqrt(2.0 * A / (mu0 * Ms * Ms));
+    const double B0 = 2.0 * A / (a * a * Ms);
+    const double t0 = 1.0 / (gamma * B0);
+    std::memset(out, 0, sizeof(*out));
+    out->alpha = alpha;
+    out->c = (a / lam) * (a / lam);
+    out->temp = kB * T_K / (2.0 * A * L);
+    out->dtau = dt_ps * 1e-12 / t0;
+    if (lambda_ex_nm) *lambda_ex_nm = lam * 1e9;
+    return 0;
+}
+
+int llg_build_kernels(double R_nm, double L_nm, double a_nm, int P_override, llg_disk* out) {
+    return create(1, &R_nm, &L_nm, a_nm, nullptr, &P_override, out);
+}
+
+int llg_batch_create(int n, const double* R_nm, const double* L_nm, double a_nm, const int* wg_per_disk,
+                     llg_disk* out) {
+    return create(n, R_nm, L_nm, a_nm, wg_per_disk, nullptr, out);
+}
+
+int llg_disk_count(llg_disk h) { return h ? h->n : fail(LLG_EINVAL, "null handle"); }
+
+int llg_disk_info(llg_disk h, int k, int* D, int* P, int* n_cells) {
+    if (!h || k < 0 || k >= h->n) return fail(LLG_EINVAL, "bad handle or disk index");
+    if (D) *D = h->D[k];
+    if (P) *P = h->P[k];
+    if (n_cells) *n_cells = h->n_cells[k];
+    return 0;
+}
+
+long long llg_disk_offset(llg_disk h, int k) {
+    if (!h || k < 0 || k >= h->n) return fail(LLG_EINVAL, "bad handle or disk index");
+    return h->m_off[k];
+}
+
+long long llg_state_size(llg_disk h) { return h ? h->state_size : fail(LLG_EINVAL, "null handle"); }
+
+int llg_disk_workgroups(llg_disk h, int k) {
+    if (!h || k < 0 || k >= h->n) return fail(LLG_EINVAL, "bad handle or disk index");
+    return h->G[k];
+}
+
+int llg_demag_field(llg_disk h, const float* m, float* H, void* stream) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!m || !H) return fail(LLG_EINVAL, "null array");
+    return launch(h, MODE_DEMAG, const_cast<float*>(m), H, 0, 0, 0, 0, (hipStream_t)stream);
+}
+
+int llg_rhs(llg_disk h, const float* m, float* dmdtau, const llg_params* p, void* stream) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!m || !dmdtau) return fail(LLG_EINVAL, "null array");
+    if ((rc = upload_params(h, p, (hipStream_t)stream))) return rc;
+    return launch(h, MODE_RHS, const_cast<float*>(m), dmdtau, 0, 0, 0, 0, (hipStream_t)stream);
+}
+
+int llg_rk4_step(llg_disk h, float* m, long long nsteps, const llg_params* p, void* stream) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!m) return fail(LLG_EINVAL, "null array");
+    if (nsteps < 0) return fail(LLG_EINVAL, "nsteps < 0");
+    if (nsteps == 0) return 0;
+    if ((rc = upload_params(h, p, (hipStream_t)stream))) return rc;
+    return launch(h, MODE_RK4, m, nullptr, nsteps, 0, 0, 0, (hipStream_t)stream);
+}
+
+int llg_heun_step(llg_disk h, float* m, long long nsteps, unsigned long long seed, unsigned long long step0,
+                  unsigned int replica, const llg_params* p, void* stream) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!m) return fail(LLG_EINVAL, "null array");
+    if (nsteps < 0) return fail(LLG_EINVAL, "nsteps < 0");
+    if (nsteps == 0) return 0;
+    if ((rc = upload_params(h, p, (hipStream_t)stream))) return rc;
+    return launch(h, MODE_HEUN, m, nullptr, nsteps, seed, step0, replica, (hipStream_t)stream);
+}
+
+int llg_noise(llg_disk h, unsigned long long seed, unsigned long long step, unsigned int replica, float* w,
+              void* stream) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!w) return fail(LLG_EINVAL, "null array");
+    hipLaunchKernelGGL(noise_kernel, dim3(64, h->n), dim3(256), 0, (hipStream_t)stream, h->desc_dev, h->n, w, seed,
+                       step, replica);
+    HIP_TRY(hipGetLastError());
+    return 0;
+}
+
+int llg_energy(llg_disk h, const float* m, const llg_params* p, double* out, void* stream) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!m || !out) return fail(LLG_EINVAL, "null array");
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = upload_params(h, p, st))) return rc;
+    if ((rc = launch(h, MODE_ENERGY, const_cast<float*>(m), nullptr, 0, 0, 0, 0, st))) return rc;
+    hipLaunchKernelGGL(energy_finalize, dim3((h->n + 63) / 64), dim3(64), 0, st, h->desc_dev, h->n, out);
+    HIP_TRY(hipGetLastError());
+    return 0;
+}
+
+int llg_vortex_core_position(llg_disk h, const float* m, double lambda_ex_nm, const double* hint_nm, double* out,
+                             void* stream) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!m || !out) return fail(LLG_EINVAL, "null array");
+    if (!(lambda_ex_nm > 0)) return fail(LLG_EINVAL, "lambda_ex must be positive");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipEventSynchronize(h->hint_event));
+    for (int k = 0; k < 2 * h->n; ++k) h->hint_pin[k] = hint_nm ? hint_nm[k] : NAN;
+    HIP_TRY(hipMemcpyAsync(h->hint_dev, h->hint_pin, 2 * h->n * sizeof(double), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(h->hint_event, st));
+    hipLaunchKernelGGL(core_kernel, dim3(h->n), dim3(OBS_THREADS), 0, st, h->desc_dev, m, h->hint_dev, h->a_nm,
+                       4.0 * lambda_ex_nm / h->a_nm, out);
+    HIP_TRY(hipGetLastError());
+    return 0;
+}
+
+int llg_mean_m(llg_disk h, const float* m, double* out, void* stream) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!m || !out) return fail(LLG_EINVAL, "null array");
+    hipLaunchKernelGGL(mean_kernel, dim3(h->n), dim3(OBS_THREADS), 0, (hipStream_t)stream, h->desc_dev, m, out);
+    HIP_TRY(hipGetLastError());
+    return 0;
+}
+
+int llg_check(llg_disk h, void* stream) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    int e = 0;
+    HIP_TRY(hipMemcpy(&e, h->err_dev, sizeof(int), hipMemcpyDeviceToHost));
+    if (e) {
+        HIP_TRY(hipMemset(h->err_dev, 0, sizeof(int)));
+        std::string msg = "device failure:";
+        if (e & ERR_BARRIER) msg += " group barrier timed out;";
+        if (e & ERR_NONFINITE) msg += " non-finite state;";
+        return fail(LLG_EDEVICE, msg);
+    }
+    return 0;
+}
+
+void llg_destroy(llg_disk h) { delete h; }
+
+const char* llg_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,258 @@
+"""GPU parity: every entry point of lib_llgdisk (through the C ABI) against the
+FP64 oracle on the same seeded inputs.
+
+Tolerance (float32 device arithmetic against float64): fields, right-hand
+sides and one-step increments agree norm-wise, ||x_gpu - x_ref||_inf /
+||x_ref||_inf <= 1e-5; states after a few steps agree to 2e-6 absolute (|m| = 1);
+integer decisions (plaquette windings, the chosen plaquette) agree exactly.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import llg_inputs as li
+import oracle
+from oracle.demag import demag_fft
+from oracle.dynamics import heun_step as o_heun, llg_rhs as o_rhs, rk4_step as o_rk4
+from oracle.observables import energy as o_energy, mean_m as o_mean, vortex_core_position as o_core
+from oracle.philox import gaussian_field
+
+pytestmark = pytest.mark.gpu
+
+C_PY = 0.14298555
+LAM_NM = 5.28906
+
+GEOMS = [  # (R nm, L nm, P override) -> D = R, spans P = 64..512, odd and even D
+    (6.0, 10.0, 0), (15.0, 5.0, 0), (30.0, 10.0, 0), (30.5, 20.0, 0), (40.0, 7.5, 0),
+    (50.0, 20.0, 0), (61.0, 12.0, 0), (100.0, 20.0, 0), (30.0, 10.0, 128), (120.0, 10.0, 512),
+]
+
+
+def gpu():
+    from paper_1207_2192_amd import Disk, LLGParams
+    return Disk, LLGParams
+
+
+def to_dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda").reshape(-1).contiguous()
+
+
+def rel(got, ref):
+    return float((got - ref).abs().max() / ref.abs().max())
+
+
+def state_in(D, seed, kind="random"):
+    if kind == "random":
+        return li.random_unit_field(D, seed)
+    if kind == "smooth":
+        return li.smooth_random_field(D, seed)
+    return li.vortex_ansatz(D, 0.13 * D + 0.37, -0.07 * D + 0.21)
+
+
+@pytest.mark.parametrize("R,L,P", GEOMS)
+def test_demag_field(R, L, P):
+    Disk, _ = gpu()
+    disk = Disk.build(R, L, 2.0, P)
+    od = oracle.Disk(R, L, 2.0, P=P or None)
+    D = disk.D[0]
+    print(f"demag R={R} L={L} D={D} P={disk.P[0]}", flush=True)
+    m0 = state_in(D, 100 + D)
+    H = disk.demag_field(to_dev(m0)).view(3, D, D).double().cpu()
+    ref = demag_fft(torch.tensor(m0), od)
+    assert rel(H, ref) <= 1e-5
+    assert float(H[:, ~od.mask].abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("R,L,P", GEOMS)
+def test_rhs(R, L, P):
+    Disk, Prm = gpu()
+    disk = Disk.build(R, L, 2.0, P)
+    od = oracle.Disk(R, L, 2.0, P=P or None)
+    D = disk.D[0]
+    print(f"rhs R={R} D={D}", flush=True)
+    m0 = state_in(D, 7 + D)
+    p = Prm(alpha=0.17, c=C_PY, hext=(0.05, -0.1, 0.2))
+    f = disk.rhs(to_dev(m0), p).view(3, D, D).double().cpu()
+    ref = o_rhs(torch.tensor(m0), od, oracle.Params(alpha=0.17, c=C_PY, hext=(0.05, -0.1, 0.2)))
+    assert rel(f, ref) <= 1e-5
+
+
+def test_inputs_outside_disk_are_ignored():
+    Disk, Prm = gpu()
+    disk = Disk.build(30.0, 10.0)
+    D = disk.D[0]
+    od = oracle.Disk(30.0, 10.0)
+    m0 = state_in(D, 3)
+    junk = m0.copy()
+    junk[:, ~od.mask.numpy()] = 5.0
+    p = Prm(alpha=0.1, c=C_PY)
+    a = disk.rhs(to_dev(m0), p)
+    b = disk.rhs(to_dev(junk), p)
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("R,L,P", [(30.0, 10.0, 0), (61.0, 12.0, 0), (100.0, 20.0, 0), (120.0, 10.0, 512)])
+def test_rk4_one_step_increment(R, L, P):
+    Disk, Prm = gpu()
+    disk = Disk.build(R, L, 2.0, P)
+    od = oracle.Disk(R, L, 2.0, P=P or None)
+    D = disk.D[0]
+    print(f"rk4 R={R} D={D}", flush=True)
+    m0 = state_in(D, 5, "vortex")
+    m = to_dev(m0)
+    disk.rk4_step(m, 1, Prm(alpha=0.01, c=C_PY, dtau=0.04))
+    got = m.view(3, D, D).double().cpu()
+    ref = o_rk4(torch.tensor(m0), od, oracle.Params(alpha=0.01, c=C_PY, dtau=0.04), 1)
+    m0t = od.apply_mask(torch.tensor(m0))
+    assert rel(got - m0t, ref - m0t) <= 1e-5
+    assert float((got - ref).abs().max()) <= 2e-6
+
+
+@pytest.mark.parametrize("renorm", [False, True])
+def test_rk4_many_steps(renorm):
+    Disk, Prm = gpu()
+    R, L = 40.0, 10.0
+    disk = Disk.build(R, L)
+    od = oracle.Disk(R, L)
+    D = disk.D[0]
+    m0 = state_in(D, 9, "vortex")
+    m = to_dev(m0)
+    disk.rk4_step(m, 25, Prm(alpha=0.02, c=C_PY, dtau=0.04, renorm=renorm))
+    disk.check()
+    ref = o_rk4(torch.tensor(m0), od, oracle.Params(alpha=0.02, c=C_PY, dtau=0.04, renorm=renorm), 25)
+    assert float((m.view(3, D, D).double().cpu() - ref).abs().max()) <= 1e-5
+
+
+def test_noise_matches_oracle_philox():
+    Disk, _ = gpu()
+    disk = Disk.build(30.0, 10.0)
+    D = disk.D[0]
+    od = oracle.Disk(30.0, 10.0)
+    for (seed, step, rep) in ((1, 0, 0), (20120827, 123456789, 7), (2**63 + 5, 2**40 + 3, 63)):
+        w = disk.noise(seed, step, rep).view(3, D, D).double().cpu()
+        ref = torch.from_numpy(gaussian_field(seed, step, rep, D)) * od.mask
+        assert float((w - ref).abs().max()) <= 2e-5 * float(ref.abs().max())
+
+
+@pytest.mark.parametrize("fd", [False, True])
+def test_heun_steps(fd):
+    Disk, Prm = gpu()
+    R, L = 30.0, 5.0
+    disk = Disk.build(R, L)
+    od = oracle.Disk(R, L)
+    D = disk.D[0]
+    m0 = state_in(D, 4, "vortex")
+    m = to_dev(m0)
+    kw = dict(alpha=0.1, c=C_PY, temp=0.0319, dtau=0.0266, renorm=True, fd_factor=fd)
+    disk.heun_step(m, 6, Prm(**kw), seed=20120827, step0=1000, replica=3)
+    ref = o_heun(torch.tensor(m0), od, oracle.Params(**kw), seed=20120827, step0=1000, replica=3, nsteps=6)
+    assert float((m.view(3, D, D).double().cpu() - ref).abs().max()) <= 5e-6
+
+
+def test_heun_restart_is_bitwise():
+    Disk, Prm = gpu()
+    disk = Disk.build(30.0, 10.0)
+    D = disk.D[0]
+    m0 = to_dev(state_in(D, 2, "vortex"))
+    p = Prm(alpha=0.1, c=C_PY, temp=0.02, dtau=0.02, renorm=True)
+    a = m0.clone()
+    disk.heun_step(a, 8, p, seed=5, step0=0, replica=1)
+    b = m0.clone()
+    disk.heun_step(b, 3, p, seed=5, step0=0, replica=1)
+    disk.heun_step(b, 5, p, seed=5, step0=3, replica=1)
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("R,L", [(30.0, 10.0), (61.0, 12.0), (100.0, 20.0)])
+def test_energy(R, L):
+    Disk, Prm = gpu()
+    disk = Disk.build(R, L)
+    od = oracle.Disk(R, L)
+    D = disk.D[0]
+    m0 = state_in(D, 8, "vortex")
+    h = (0.01, -0.02, 0.03)
+    e = disk.energy(to_dev(m0), Prm(c=C_PY, hext=h)).cpu()[0]
+    m32 = torch.tensor(m0, dtype=torch.float32).double()
+    ref = o_energy(m32, od, oracle.Params(c=C_PY, hext=h))
+    for k in range(4):
+        assert abs(float(e[k]) - ref[k]) <= 1e-6 * abs(ref[0]) + 1e-12
+    assert abs(float(e[0]) - float(e[1] + e[2] + e[3])) < 1e-9 * abs(ref[0])
+
+
+@pytest.mark.parametrize("x0,y0,hint", [(3.3, -1.7, None), (-5.2, 4.4, None), (0.2, 0.1, (0.5, 0.2)),
+                                        (9.6, 2.8, None)])
+def test_core_position(x0, y0, hint):
+    Disk, _ = gpu()
+    disk = Disk.build(40.0, 10.0)
+    od = oracle.Disk(40.0, 10.0)
+    D = disk.D[0]
+    m0 = li.vortex_ansatz(D, x0, y0)
+    m32 = torch.tensor(m0, dtype=torch.float32)
+    out = disk.vortex_core_position(to_dev(m0), LAM_NM, hint).cpu()[0]
+    ref = o_core(m32.double(), od, LAM_NM, hint)
+    assert int(out[4]) == ref[4]
+    for k in range(4):
+        assert abs(float(out[k]) - ref[k]) <= 1e-9 * max(1.0, abs(ref[k]))
+
+
+def test_core_position_without_vortex_and_with_several():
+    Disk, _ = gpu()
+    disk = Disk.build(40.0, 10.0)
+    od = oracle.Disk(40.0, 10.0)
+    D = disk.D[0]
+    for seed in (1, 2, 3):
+        m0 = li.random_unit_field(D, seed)        # many +1 and -1 plaquettes
+        m32 = torch.tensor(m0, dtype=torch.float32)
+        out = disk.vortex_core_position(to_dev(m0), LAM_NM).cpu()[0]
+        ref = o_core(m32.double(), od, LAM_NM)
+        assert int(out[4]) == ref[4]
+        for k in range(4):
+            assert abs(float(out[k]) - ref[k]) <= 1e-9 * max(1.0, abs(ref[k]))
+    m0 = np.zeros((3, D, D)); m0[0] = 1.0; m0[2] = 0.1
+    out = disk.vortex_core_position(to_dev(m0), LAM_NM).cpu()[0]
+    assert int(out[4]) == 0 and math.isnan(float(out[2]))
+
+
+def test_mean_m():
+    Disk, _ = gpu()
+    disk = Disk.build(30.0, 10.0)
+    od = oracle.Disk(30.0, 10.0)
+    D = disk.D[0]
+    m0 = li.random_unit_field(D, 12)
+    got = disk.mean_m(to_dev(m0)).cpu()[0]
+    ref = o_mean(torch.tensor(m0, dtype=torch.float32).double(), od)
+    for k in range(3):
+        assert abs(float(got[k]) - ref[k]) < 1e-12
+
+
+def test_ragged_batch_matches_single_disks():
+    Disk, Prm = gpu()
+    Rs = [30.0, 61.0, 40.0, 15.0, 100.0, 30.0]
+    Ls = [10.0, 12.0, 4.0, 5.0, 20.0, 10.0]
+    batch = Disk.batch(Rs, Ls)
+    states = [li.vortex_ansatz(int(2 * R / 2), 1.3 + k, -0.7) for k, R in enumerate(Rs)]
+    m = batch.pack([to_dev(s) for s in states])
+    ps = [Prm(alpha=0.02 * (k + 1), c=C_PY, dtau=0.04) for k in range(len(Rs))]
+    batch.rk4_step(m, 3, ps)
+    batch.check()
+    for k, (R, L) in enumerate(zip(Rs, Ls)):
+        od = oracle.Disk(R, L)
+        ref = o_rk4(torch.tensor(states[k]), od, oracle.Params(alpha=0.02 * (k + 1), c=C_PY, dtau=0.04), 3)
+        got = batch.unpack(m, k).double().cpu()
+        assert float((got - ref).abs().max()) <= 2e-6, k
+
+
+def test_bad_geometry_is_rejected():
+    from paper_1207_2192_amd._lib import LLGError
+    Disk, _ = gpu()
+    with pytest.raises(LLGError):
+        Disk.build(30.3, 10.0)          # 2R/a not an integer
+    with pytest.raises(LLGError):
+        Disk.build(100.0, 10.0, 2.0, 128)   # P < 2D - 1
+    with pytest.raises(LLGError):
+        Disk.build(30.0, -1.0)
+    disk = Disk.build(30.0, 10.0)
+    with pytest.raises(ValueError):
+        disk.demag_field(torch.zeros(10, device="cuda"))
