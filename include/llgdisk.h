@@ -111,6 +111,16 @@ long long llg_state_size(llg_disk h);
 /* Workgroups assigned to disk k (host). */
 int llg_disk_workgroups(llg_disk h, int k);
 
+/* Re-plan the persistent launch of h (host; synchronises the device):
+ * unit_groups = 1, 2 or 4 groups of three wavefronts per workgroup (each
+ * group carries one transform per field component at a time), and the number
+ * of workgroups per disk (wg_per_disk, host, n entries; NULL = the library's
+ * choice).  Results do not depend on the plan; the tuner uses this. */
+int llg_tune(llg_disk h, int unit_groups, const int* wg_per_disk);
+
+/* Current launch shape (host): unit groups, total workgroups, threads per workgroup. */
+int llg_launch_shape(llg_disk h, int* unit_groups, int* workgroups, int* threads);
+
 /* Demagnetisation field H^M / Ms of state m (Sec. II.B): H[k] = sum over the
  * disk of K(r_i - r_j) m_j, written to H (packed like m). */
 int llg_demag_field(llg_disk h, const float* m, float* H, void* stream);

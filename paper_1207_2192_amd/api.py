@@ -95,6 +95,19 @@ class Disk:
         check(lib.llg_batch_create(n, R, L, a_nm, W, ctypes.byref(h)), "llg_batch_create")
         return cls(h, dev)
 
+    def tune(self, unit_groups: int, wg_per_disk=None):
+        """Re-plan the persistent launch (llg_tune); results do not depend on it."""
+        lib = _lib.load()
+        W = None if wg_per_disk is None else (ctypes.c_int * self.n)(*[int(w) for w in wg_per_disk])
+        check(lib.llg_tune(self._h, int(unit_groups), W), "llg_tune")
+        self.workgroups = [lib.llg_disk_workgroups(self._h, k) for k in range(self.n)]
+
+    def launch_shape(self):
+        ug, nwg, nt = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(_lib.load().llg_launch_shape(self._h, ctypes.byref(ug), ctypes.byref(nwg), ctypes.byref(nt)),
+              "llg_launch_shape")
+        return ug.value, nwg.value, nt.value
+
     def close(self):
         if self._h:
             _lib.load().llg_destroy(self._h)

@@ -8,10 +8,11 @@
 
 namespace llg {
 
-constexpr int WG_THREADS = 192;   // three wavefronts: components x, y, z (or packed row pairs)
+constexpr int WG_THREADS = 192;   // one group of three wavefronts: components x, y, z (or packed row pairs)
+constexpr int MAX_UG = 4;         // wavefront groups per workgroup
 constexpr int MAX_P = 512;
 constexpr int MAX_R = 8;
-constexpr int LDS_FFT = 3 * 64 * MAX_R;   // float2 slots: 3 waves x (64/Tf units) x P = 3*64*R
+constexpr int LDS_FFT = 3 * 64 * MAX_R;   // float2 slots per group: 3 waves x (64/Tf units) x P = 3*64*R
 
 // Per-disk descriptor (device memory, written once by the host).
 struct DiskDesc {
@@ -108,11 +109,13 @@ __device__ __forceinline__ bool group_barrier(unsigned int* bar, unsigned int ta
     if (G == 1) return true;
     __shared__ int s_ok;
     if (threadIdx.x == 0) {
-        __threadfence();
-        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        // one release (L2 write-back) before arriving, relaxed polling that
+        // bypasses the caches without invalidating them, one acquire after
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         unsigned int spins = 0;
         int ok = 1;
-        while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(1);
             if (++spins > SPIN_LIMIT) {
                 ok = 0;
@@ -120,7 +123,7 @@ __device__ __forceinline__ bool group_barrier(unsigned int* bar, unsigned int ta
                 break;
             }
         }
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         s_ok = ok;
     }
     __syncthreads();

@@ -22,20 +22,22 @@
 
 namespace llg {
 
-template <int P, int R>
+template <int P, int R, int UG>
 __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, const DiskPrm& pr, int g,
                                          float2* lds, float2* ltw) {
     constexpr int Tf = P / R;
-    constexpr int U = 64 / Tf;
+    constexpr int U = UG * (64 / Tf);          // transforms per component in flight per workgroup
+    constexpr int NT = WG_THREADS * UG;
     constexpr int H = P / 2 + 1;
     const int D = d.D, Dp = d.Dp, G = d.G;
     const int DD = D * D;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int u = lane / Tf, t = lane - u * Tf;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = wv % 3, grp = wv / 3;     // wave = component (or packed row) of the group
+    const int u = grp * (64 / Tf) + lane / Tf, t = lane % Tf;
     float2* const mybuf = lds + (wave * U + u) * P;
 #define BUF(w, uu) (lds + ((w) * U + (uu)) * P)
 
-    for (int i = threadIdx.x; i < P; i += WG_THREADS) ltw[i] = d.tw[i];
+    for (int i = threadIdx.x; i < P; i += NT) ltw[i] = d.tw[i];
     __syncthreads();
 
     float* const m = a.m + d.m_off;
@@ -49,7 +51,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
 
     // ---- packed rows of a state into LDS (masked), columns [0, D)
     auto load_state_rows = [&](int b, const float* src) {
-        for (int idx = threadIdx.x; idx < U * D; idx += WG_THREADS) {
+        for (int idx = threadIdx.x; idx < U * D; idx += NT) {
             const int uu = idx / D, i = idx - uu * D;
             const int p = b * U + uu, j0 = 2 * p, j1 = j0 + 1;
             float x0 = 0.f, y0 = 0.f, z0 = 0.f, x1 = 0.f, y1 = 0.f, z1 = 0.f;
@@ -85,7 +87,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             v[j] = (i < D) ? mybuf[i] : make_float2(0.f, 0.f);
         }
         fft_run<P, R, false>(v, mybuf, ltw, t);
-        for (int idx = threadIdx.x; idx < U * H; idx += WG_THREADS) {
+        for (int idx = threadIdx.x; idx < U * H; idx += NT) {
             const int uu = idx / H, k = idx - uu * H;
             const int p = b * U + uu;
             if (p >= d.n_pairs) continue;
@@ -120,7 +122,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             v[j] = (valid && i < D) ? col[i] : make_float2(0.f, 0.f);
         }
         fft_run<P, R, false>(v, mybuf, ltw, t);
-        for (int idx = threadIdx.x; idx < U * P; idx += WG_THREADS) {
+        for (int idx = threadIdx.x; idx < U * P; idx += NT) {
             const int uu = idx / P, ky = idx - uu * P;
             const int kxx = b * U + uu;
             if (kxx >= H) continue;
@@ -145,7 +147,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
 
     // ---- rebuild the full-length row spectra of a pair and transform back along x
     auto row_inverse = [&](int b) {
-        for (int idx = threadIdx.x; idx < U * H; idx += WG_THREADS) {
+        for (int idx = threadIdx.x; idx < U * H; idx += NT) {
             const int uu = idx / H, k = idx - uu * H;
             const int p = b * U + uu;
             float4 sx = make_float4(0.f, 0.f, 0.f, 0.f), sy = sx, sz = sx;
@@ -179,7 +181,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     // ---- per-cell work after the inverse transforms; new stage state back into LDS
     // stage s of step n; Ys = state whose field is in LDS; Yn = where the next stage state goes
     auto cell_update = [&](int b, int s, long long n, const float* Ys, float* Yn) {
-        for (int idx = threadIdx.x; idx < U * D; idx += WG_THREADS) {
+        for (int idx = threadIdx.x; idx < U * D; idx += NT) {
             const int uu = idx / D, i = idx - uu * D;
             const int p = b * U + uu;
             if (p >= d.n_pairs) continue;
@@ -340,17 +342,19 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             cell_update(b, 0, 0, m, nullptr);
         }
         if (mode == MODE_ENERGY) {
-            __shared__ double red[3][3];
+            __shared__ double red[3 * MAX_UG][3];
             const double s0 = wave_sum(e_ex), s1 = wave_sum(e_dm), s2 = wave_sum(e_ext);
             if (lane == 0) {
-                red[wave][0] = s0;
-                red[wave][1] = s1;
-                red[wave][2] = s2;
+                red[wv][0] = s0;
+                red[wv][1] = s1;
+                red[wv][2] = s2;
             }
             __syncthreads();
             if (threadIdx.x < 3) {
                 const int q = threadIdx.x;
-                d.part[g * 4 + q] = red[0][q] + red[1][q] + red[2][q];
+                double acc = 0.0;
+                for (int w = 0; w < 3 * UG; ++w) acc += red[w][q];
+                d.part[g * 4 + q] = acc;
             }
         }
         return;
@@ -382,8 +386,9 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
 #undef BUF
 }
 
-__global__ __launch_bounds__(WG_THREADS) void llg_persistent(KArgs a) {
-    __shared__ float2 lds[LDS_FFT];
+template <int UG>
+__global__ __launch_bounds__(WG_THREADS* UG) void llg_persistent(KArgs a) {
+    __shared__ float2 lds[LDS_FFT * UG];
     __shared__ float2 ltw[MAX_P];
     const int wg = blockIdx.x;
     const int di = a.wg2disk[wg];
@@ -392,10 +397,10 @@ __global__ __launch_bounds__(WG_THREADS) void llg_persistent(KArgs a) {
     const DiskDesc d = a.disks[di];
     const DiskPrm pr = a.prm[di];
     switch (d.P) {
-        case 64: run_disk<64, 4>(a, d, pr, g, lds, ltw); break;
-        case 128: run_disk<128, 4>(a, d, pr, g, lds, ltw); break;
-        case 256: run_disk<256, 4>(a, d, pr, g, lds, ltw); break;
-        case 512: run_disk<512, 8>(a, d, pr, g, lds, ltw); break;
+        case 64: run_disk<64, 4, UG>(a, d, pr, g, lds, ltw); break;
+        case 128: run_disk<128, 4, UG>(a, d, pr, g, lds, ltw); break;
+        case 256: run_disk<256, 4, UG>(a, d, pr, g, lds, ltw); break;
+        case 512: run_disk<512, 8, UG>(a, d, pr, g, lds, ltw); break;
         default: break;
     }
 }

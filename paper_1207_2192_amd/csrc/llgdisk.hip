@@ -159,6 +159,8 @@ struct llg_disk_s {
     unsigned int* bars = nullptr;
     int n_bars = 0;
     int* err_dev = nullptr;
+    int UG = 1;                       // wavefront groups per workgroup of the persistent launch
+    std::vector<DiskDesc> desc;       // host copy of the descriptors
 
     ~llg_disk_s() {
         for (void* p : allocs) (void)hipFree(p);
@@ -176,16 +178,31 @@ struct llg_disk_s {
         *p = static_cast<T*>(q);
         return 0;
     }
+    void dfree(void* p) {
+        if (!p) return;
+        auto it = std::find(allocs.begin(), allocs.end(), p);
+        if (it != allocs.end()) {
+            (void)hipFree(p);
+            allocs.erase(it);
+        }
+    }
 };
 
 namespace {
 
-int max_coresident_workgroups(int* out) {
+const void* persistent_kernel(int UG) {
+    switch (UG) {
+        case 1: return reinterpret_cast<const void*>(llg_persistent<1>);
+        case 2: return reinterpret_cast<const void*>(llg_persistent<2>);
+        default: return reinterpret_cast<const void*>(llg_persistent<4>);
+    }
+}
+
+int max_coresident_workgroups(int UG, int* out) {
     int dev = 0, ncu = 0, per_cu = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(llg_persistent),
-                                                         WG_THREADS, 0));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel(UG), WG_THREADS * UG, 0));
     *out = ncu * per_cu;
     return 0;
 }
@@ -202,6 +219,131 @@ int choose_P(int D, int P_override, int* P) {
     if (*P != 64 && *P != 128 && *P != 256 && *P != 512)
         return fail(LLG_EUNSUPPORTED, "FFT size " + std::to_string(*P) + " unsupported (64, 128, 256 or 512; disks up to D = 256)");
     if (*P < need) return fail(LLG_EINVAL, "P = " + std::to_string(*P) + " < 2D-1 = " + std::to_string(need));
+    return 0;
+}
+
+// Units (transforms per component) a workgroup carries at once, for FFT size P.
+int units_per_wg(int P, int UG) { return UG * (64 / (P / radix_for(P))); }
+
+int default_unit_groups(llg_disk h) {
+    // a lone disk wants few, wide workgroups (each group barrier costs about
+    // 0.35 us per workgroup per XCD); a batch of many disks wants one narrow
+    // workgroup group per small disk
+    return h->n == 1 ? 4 : 1;
+}
+
+// Workgroups per disk and the workgroup-to-disk map of the persistent launch.
+int plan(llg_disk h, int UG, const int* wg_per_disk) {
+    if (UG != 1 && UG != 2 && UG != 4) return fail(LLG_EINVAL, "unit groups must be 1, 2 or 4");
+    const int n = h->n;
+    int cap = 0;
+    int rc = max_coresident_workgroups(UG, &cap);
+    if (rc) return rc;
+    std::vector<int> useful(n), G(n);
+    std::vector<double> work(n);
+    for (int k = 0; k < n; ++k) {
+        const int P = h->P[k], D = h->D[k];
+        const int U = units_per_wg(P, UG);
+        const int H = P / 2 + 1;
+        const int n_pairs = (D + 1) / 2;
+        useful[k] = std::max((n_pairs + U - 1) / U, (H + U - 1) / U);
+        work[k] = (double)(n_pairs + H) * P * std::log2((double)P);
+    }
+    if (wg_per_disk) {
+        for (int k = 0; k < n; ++k) {
+            if (wg_per_disk[k] < 1) return fail(LLG_EINVAL, "wg_per_disk must be >= 1");
+            G[k] = std::min(wg_per_disk[k], useful[k]);
+        }
+    } else {
+        const double wsum = std::accumulate(work.begin(), work.end(), 0.0);
+        for (int k = 0; k < n; ++k)
+            G[k] = std::max(1, std::min(useful[k], (int)std::floor(cap * work[k] / wsum)));
+    }
+    long long total = std::accumulate(G.begin(), G.end(), 0LL);
+    while (total > cap) {  // trim the disks with the most workgroups
+        int kmax = (int)(std::max_element(G.begin(), G.end()) - G.begin());
+        if (G[kmax] <= 1) break;
+        --G[kmax];
+        --total;
+    }
+    if (total > cap)
+        return fail(LLG_EUNSUPPORTED, "batch needs " + std::to_string(total) + " workgroups but only " +
+                                          std::to_string(cap) + " can be co-resident");
+
+    // Disks whose workgroups all fit one XCD stay on one XCD (workgroup w runs
+    // on XCD w mod 8); larger disks take consecutive ids and span the XCDs.
+    constexpr int NXCD = 8;
+    std::vector<int> w2d, w2l;
+    {
+        std::vector<std::vector<std::pair<int, int>>> lanes(NXCD);
+        std::vector<long long> load(NXCD, 0);
+        std::vector<int> big;
+        std::vector<int> order(n);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return G[x] > G[y]; });
+        for (int k : order) {
+            if (n > 1 && G[k] * NXCD <= cap) {
+                const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                for (int l = 0; l < G[k]; ++l) lanes[x].push_back({k, l});
+                load[x] += (long long)G[k] * (long long)work[k];
+            } else {
+                big.push_back(k);
+            }
+        }
+        for (int k : big)
+            for (int l = 0; l < G[k]; ++l) {
+                w2d.push_back(k);
+                w2l.push_back(l);
+            }
+        while (w2d.size() % NXCD) {
+            w2d.push_back(-1);
+            w2l.push_back(0);
+        }
+        size_t depth = 0;
+        for (auto& l : lanes) depth = std::max(depth, l.size());
+        for (size_t s = 0; s < depth; ++s)
+            for (int x = 0; x < NXCD; ++x) {
+                if (s < lanes[x].size()) {
+                    w2d.push_back(lanes[x][s].first);
+                    w2l.push_back(lanes[x][s].second);
+                } else {
+                    w2d.push_back(-1);
+                    w2l.push_back(0);
+                }
+            }
+        while (!w2d.empty() && w2d.back() < 0) {
+            w2d.pop_back();
+            w2l.pop_back();
+        }
+    }
+    if ((int)w2d.size() > cap) {  // the XCD-aligned layout does not fit: consecutive ids
+        w2d.clear();
+        w2l.clear();
+        for (int k = 0; k < n; ++k)
+            for (int l = 0; l < G[k]; ++l) {
+                w2d.push_back(k);
+                w2l.push_back(l);
+            }
+    }
+    h->dfree(h->wg2disk);
+    h->dfree(h->wg2local);
+    h->wg2disk = h->wg2local = nullptr;
+    if ((rc = h->dalloc(&h->wg2disk, w2d.size()))) return rc;
+    if ((rc = h->dalloc(&h->wg2local, w2l.size()))) return rc;
+    HIP_TRY(hipMemcpy(h->wg2disk, w2d.data(), w2d.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(h->wg2local, w2l.data(), w2l.size() * sizeof(int), hipMemcpyHostToDevice));
+    h->n_wg = (int)w2d.size();
+    for (int k = 0; k < n; ++k) {
+        DiskDesc& d = h->desc[k];
+        h->dfree(d.part);
+        d.part = nullptr;
+        if ((rc = h->dalloc(&d.part, (size_t)4 * G[k]))) return rc;
+        d.G = G[k];
+    }
+    h->G = G;
+    h->UG = UG;
+    if (!h->desc_dev && (rc = h->dalloc(&h->desc_dev, n))) return rc;
+    HIP_TRY(hipMemcpy(h->desc_dev, h->desc.data(), n * sizeof(DiskDesc), hipMemcpyHostToDevice));
     return 0;
 }
 
@@ -269,124 +411,21 @@ int create(int n, const double* R_nm, const double* L_nm, double a_nm, const int
         h->state_size += 3LL * D * D;
     }
 
-    // ---- workgroups per disk
-    int cap = 0;
-    int rc = max_coresident_workgroups(&cap);
-    if (rc) return bail(rc);
-    std::vector<int> useful(n), G(n);
-    std::vector<double> work(n);
-    for (int k = 0; k < n; ++k) {
-        const int P = h->P[k], D = h->D[k];
-        const int U = 64 / (P / radix_for(P));
-        const int H = P / 2 + 1;
-        const int n_pairs = (D + 1) / 2;
-        useful[k] = std::max((n_pairs + U - 1) / U, (H + U - 1) / U);
-        work[k] = (double)((n_pairs + U - 1) / U + (H + U - 1) / U) * P * std::log2((double)P);
-    }
-    if (wg_per_disk) {
-        for (int k = 0; k < n; ++k) {
-            if (wg_per_disk[k] < 1) return bail(fail(LLG_EINVAL, "wg_per_disk must be >= 1"));
-            G[k] = std::min(wg_per_disk[k], useful[k]);
-        }
-    } else {
-        const double wsum = std::accumulate(work.begin(), work.end(), 0.0);
-        for (int k = 0; k < n; ++k)
-            G[k] = std::max(1, std::min(useful[k], (int)std::floor(cap * work[k] / wsum)));
-    }
-    long long total = std::accumulate(G.begin(), G.end(), 0LL);
-    while (total > cap) {  // trim the disks with the most workgroups
-        int kmax = (int)(std::max_element(G.begin(), G.end()) - G.begin());
-        if (G[kmax] <= 1) break;
-        --G[kmax];
-        --total;
-    }
-    if (total > cap)
-        return bail(fail(LLG_EUNSUPPORTED, "batch needs " + std::to_string(total) + " workgroups but only " +
-                                               std::to_string(cap) + " can be co-resident"));
-    h->G = G;
-
-    // ---- workgroup map: disks whose workgroups fit one XCD stay on one XCD
-    // (workgroup w is dispatched to XCD w mod 8); larger disks take consecutive ids.
-    constexpr int NXCD = 8;
-    std::vector<int> w2d, w2l;
-    {
-        std::vector<std::vector<std::pair<int, int>>> lanes(NXCD);  // per XCD: (disk, local)
-        std::vector<long long> load(NXCD, 0);
-        std::vector<int> big;
-        std::vector<int> order(n);
-        std::iota(order.begin(), order.end(), 0);
-        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return G[x] > G[y]; });
-        for (int k : order) {
-            if (n > 1 && G[k] * NXCD <= cap) {
-                const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-                for (int l = 0; l < G[k]; ++l) lanes[x].push_back({k, l});
-                load[x] += G[k];
-            } else {
-                big.push_back(k);
-            }
-        }
-        for (int k : big)
-            for (int l = 0; l < G[k]; ++l) {
-                w2d.push_back(k);
-                w2l.push_back(l);
-            }
-        const int base = (int)w2d.size();
-        const int pad = (NXCD - base % NXCD) % NXCD;
-        for (int i = 0; i < pad; ++i) {
-            w2d.push_back(-1);
-            w2l.push_back(0);
-        }
-        size_t depth = 0;
-        for (auto& l : lanes) depth = std::max(depth, l.size());
-        const size_t start = w2d.size();
-        for (size_t s = 0; s < depth; ++s)
-            for (int x = 0; x < NXCD; ++x) {
-                // id = start + s*8 + x, and start is a multiple of 8, so id mod 8 == x
-                if (s < lanes[x].size()) {
-                    w2d.push_back(lanes[x][s].first);
-                    w2l.push_back(lanes[x][s].second);
-                } else {
-                    w2d.push_back(-1);
-                    w2l.push_back(0);
-                }
-            }
-        (void)start;
-        while (!w2d.empty() && w2d.back() < 0) {
-            w2d.pop_back();
-            w2l.pop_back();
-        }
-    }
-    if ((int)w2d.size() > cap) {
-        // the padded layout does not fit: fall back to consecutive ids
-        w2d.clear();
-        w2l.clear();
-        for (int k = 0; k < n; ++k)
-            for (int l = 0; l < G[k]; ++l) {
-                w2d.push_back(k);
-                w2l.push_back(l);
-            }
-    }
-    h->n_wg = (int)w2d.size();
-    if ((rc = h->dalloc(&h->wg2disk, w2d.size()))) return bail(rc);
-    if ((rc = h->dalloc(&h->wg2local, w2l.size()))) return bail(rc);
-    HIP_TRY(hipMemcpy(h->wg2disk, w2d.data(), w2d.size() * sizeof(int), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(h->wg2local, w2l.data(), w2l.size() * sizeof(int), hipMemcpyHostToDevice));
-
-    // ---- workspaces and descriptors
+    // ---- per-disk workspaces
+    int rc = 0;
     h->n_bars = n * 32;  // one 128-byte line per disk
     if ((rc = h->dalloc(&h->bars, h->n_bars))) return bail(rc);
     if ((rc = h->dalloc(&h->err_dev, 1))) return bail(rc);
     HIP_TRY(hipMemset(h->err_dev, 0, sizeof(int)));
-    std::vector<DiskDesc> desc(n);
+    h->desc.assign(n, DiskDesc{});
     for (int k = 0; k < n; ++k) {
-        DiskDesc& d = desc[k];
+        DiskDesc& d = h->desc[k];
         const Geom& g = h->geoms[h->geom_of[k]];
         d.D = h->D[k];
         d.P = h->P[k];
         d.H = d.P / 2 + 1;
         d.Dp = d.D + (d.D & 1);
         d.n_pairs = (d.D + 1) / 2;
-        d.G = G[k];
         d.n_cells = g.n_cells;
         d.k = k;
         d.m_off = h->m_off[k];
@@ -396,14 +435,12 @@ int create(int n, const double* R_nm, const double* L_nm, double a_nm, const int
         if ((rc = h->dalloc(&d.acc, 3 * DD))) return bail(rc);
         if ((rc = h->dalloc(&d.S, (size_t)3 * d.H * d.Dp))) return bail(rc);
         HIP_TRY(hipMemset(d.S, 0, (size_t)3 * d.H * d.Dp * sizeof(float2)));
-        if ((rc = h->dalloc(&d.part, (size_t)4 * d.G))) return bail(rc);
         d.spec = g.spec;
         d.mask = g.mask;
         d.tw = h->twiddles[d.P];
         d.bar = h->bars + 32 * k;
     }
-    if ((rc = h->dalloc(&h->desc_dev, n))) return bail(rc);
-    HIP_TRY(hipMemcpy(h->desc_dev, desc.data(), n * sizeof(DiskDesc), hipMemcpyHostToDevice));
+    if ((rc = plan(h, default_unit_groups(h), wg_per_disk))) return bail(rc);
     if ((rc = h->dalloc(&h->prm_dev, n))) return bail(rc);
     if ((rc = h->dalloc(&h->hint_dev, 2 * (size_t)n))) return bail(rc);
     HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->prm_pin), n * sizeof(DiskPrm), hipHostMallocDefault));
@@ -470,8 +507,8 @@ int launch(llg_disk h, int mode, float* m, float* out, long long nsteps, unsigne
     a.mode = mode;
     a.err = h->err_dev;
     void* args[] = {&a};
-    HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(llg_persistent), dim3(h->n_wg),
-                                       dim3(WG_THREADS), args, 0, st));
+    HIP_TRY(hipLaunchCooperativeKernel(persistent_kernel(h->UG), dim3(h->n_wg), dim3(WG_THREADS * h->UG), args, 0,
+                                       st));
     return 0;
 }
 
@@ -535,6 +572,21 @@ long long llg_state_size(llg_disk h) { return h ? h->state_size : fail(LLG_EINVA
 int llg_disk_workgroups(llg_disk h, int k) {
     if (!h || k < 0 || k >= h->n) return fail(LLG_EINVAL, "bad handle or disk index");
     return h->G[k];
+}
+
+int llg_tune(llg_disk h, int unit_groups, const int* wg_per_disk) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    HIP_TRY(hipDeviceSynchronize());
+    return plan(h, unit_groups, wg_per_disk);
+}
+
+int llg_launch_shape(llg_disk h, int* unit_groups, int* workgroups, int* threads) {
+    if (!h) return fail(LLG_EINVAL, "null handle");
+    if (unit_groups) *unit_groups = h->UG;
+    if (workgroups) *workgroups = h->n_wg;
+    if (threads) *threads = WG_THREADS * h->UG;
+    return 0;
 }
 
 int llg_demag_field(llg_disk h, const float* m, float* H, void* stream) {

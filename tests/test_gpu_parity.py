@@ -25,7 +25,7 @@ C_PY = 0.14298555
 LAM_NM = 5.28906
 
 GEOMS = [  # (R nm, L nm, P override) -> D = R, spans P = 64..512, odd and even D
-    (6.0, 10.0, 0), (15.0, 5.0, 0), (30.0, 10.0, 0), (30.5, 20.0, 0), (40.0, 7.5, 0),
+    (6.0, 10.0, 0), (15.0, 5.0, 0), (30.0, 10.0, 0), (31.0, 20.0, 0), (40.0, 7.5, 0),
     (50.0, 20.0, 0), (61.0, 12.0, 0), (100.0, 20.0, 0), (30.0, 10.0, 128), (120.0, 10.0, 512),
 ]
 
@@ -102,11 +102,13 @@ def test_rk4_one_step_increment(R, L, P):
     print(f"rk4 R={R} D={D}", flush=True)
     m0 = state_in(D, 5, "vortex")
     m = to_dev(m0)
+    m32 = od.apply_mask(m.view(3, D, D).double().cpu())      # the float32 input, exactly
     disk.rk4_step(m, 1, Prm(alpha=0.01, c=C_PY, dtau=0.04))
     got = m.view(3, D, D).double().cpu()
-    ref = o_rk4(torch.tensor(m0), od, oracle.Params(alpha=0.01, c=C_PY, dtau=0.04), 1)
-    m0t = od.apply_mask(torch.tensor(m0))
-    assert rel(got - m0t, ref - m0t) <= 1e-5
+    ref = o_rk4(m32, od, oracle.Params(alpha=0.01, c=C_PY, dtau=0.04), 1)
+    # the increment agrees to 1e-5 of its size plus the float32 rounding of the stored state
+    dg, dr = got - m32, ref - m32
+    assert float((dg - dr).abs().max()) <= 1e-5 * float(dr.abs().max()) + 2.0 ** -23
     assert float((got - ref).abs().max()) <= 2e-6
 
 
@@ -256,3 +258,22 @@ def test_bad_geometry_is_rejected():
     disk = Disk.build(30.0, 10.0)
     with pytest.raises(ValueError):
         disk.demag_field(torch.zeros(10, device="cuda"))
+
+
+def test_launch_plan_does_not_change_results():
+    # each transform is computed the same way whichever workgroup carries it,
+    # so every plan gives bit-identical states
+    Disk, Prm = gpu()
+    disk = Disk.build(61.0, 12.0)
+    D = disk.D[0]
+    m0 = to_dev(state_in(D, 3, "vortex"))
+    p = Prm(alpha=0.05, c=C_PY, dtau=0.04)
+    outs = []
+    for ug, wg in ((1, None), (1, [7]), (2, [5]), (4, [3]), (4, None), (2, [1])):
+        disk.tune(ug, wg)
+        m = m0.clone()
+        disk.rk4_step(m, 6, p)
+        disk.check()
+        outs.append(m)
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
