@@ -97,6 +97,45 @@ __device__ __forceinline__ float3 thermal_normals(unsigned long long seed, unsig
     return make_float3(r01 * c1f, r01 * s1, r23 * c3f);
 }
 
+// ---------------------------------------------------------------- shared buffers
+// Buffers that one workgroup writes and another reads inside a launch (row and
+// column spectra, stage states) are accessed only through device-scope relaxed
+// atomic loads and stores.  On gfx950 these carry the system-coherence bit:
+// stores are written through to the device coherence point and loads are
+// served from it, so no L2 write-back or invalidate is needed at a barrier;
+// the barrier only has to drain the stores (s_waitcnt vmcnt(0)) before it
+// signals arrival.  Read-only data (kernel spectra, masks, twiddles) keeps the
+// normal cached path.
+__device__ __forceinline__ float ld_sh(const float* p) {
+    return __uint_as_float(__hip_atomic_load(reinterpret_cast<const unsigned int*>(p), __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ void st_sh(float* p, float v) {
+    __hip_atomic_store(reinterpret_cast<unsigned int*>(p), __float_as_uint(v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float2 ld_sh2(const float2* p) {
+    const unsigned long long u = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+    return make_float2(__uint_as_float((unsigned int)u), __uint_as_float((unsigned int)(u >> 32)));
+}
+__device__ __forceinline__ void st_sh2(float2* p, float2 v) {
+    const unsigned long long u =
+        (unsigned long long)__float_as_uint(v.x) | ((unsigned long long)__float_as_uint(v.y) << 32);
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float4 ld_sh4(const float2* p) {
+    const float2 a = ld_sh2(p), b = ld_sh2(p + 1);
+    return make_float4(a.x, a.y, b.x, b.y);
+}
+__device__ __forceinline__ void st_sh4(float2* p, float4 v) {
+    st_sh2(p, make_float2(v.x, v.y));
+    st_sh2(p + 1, make_float2(v.z, v.w));
+}
+
+// Wait until every store this wave issued has completed.
+__device__ __forceinline__ void drain_stores() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
 // ---------------------------------------------------------------- group barrier
 // All workgroups that step one disk meet here.  The counter only grows during
 // a launch (it is cleared before each launch); `target` = epoch * G.  A wait
@@ -105,13 +144,11 @@ __device__ __forceinline__ float3 thermal_normals(unsigned long long seed, unsig
 constexpr unsigned int SPIN_LIMIT = 1u << 22;
 
 __device__ __forceinline__ bool group_barrier(unsigned int* bar, unsigned int target, int G, int* err) {
+    drain_stores();
     __syncthreads();
     if (G == 1) return true;
     __shared__ int s_ok;
     if (threadIdx.x == 0) {
-        // one release (L2 write-back) before arriving, relaxed polling that
-        // bypasses the caches without invalidating them, one acquire after
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         unsigned int spins = 0;
         int ok = 1;
@@ -123,7 +160,6 @@ __device__ __forceinline__ bool group_barrier(unsigned int* bar, unsigned int ta
                 break;
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         s_ok = ok;
     }
     __syncthreads();

@@ -22,6 +22,15 @@
 
 namespace llg {
 
+// Disk membership of cell (j, i) of a D x D box, in exact integer arithmetic:
+// the cell centre ((i-(D-1)/2), (j-(D-1)/2)) lies inside or on the circle of
+// radius D/2.  Same rule as the host-built mask; computed in registers so
+// that no load sits in front of the state loads.
+__device__ __forceinline__ bool in_disk(int j, int i, int D) {
+    const int x = 2 * i - (D - 1), y = 2 * j - (D - 1);
+    return x * x + y * y <= D * D;
+}
+
 template <int P, int R, int UG>
 __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, const DiskPrm& pr, int g,
                                          float2* lds, float2* ltw) {
@@ -57,17 +66,17 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             float x0 = 0.f, y0 = 0.f, z0 = 0.f, x1 = 0.f, y1 = 0.f, z1 = 0.f;
             if (p < d.n_pairs) {
                 const int c0 = j0 * D + i;
-                if (mask[c0]) {
-                    x0 = src[c0];
-                    y0 = src[DD + c0];
-                    z0 = src[2 * DD + c0];
+                if (in_disk(j0, i, D)) {
+                    x0 = ld_sh(src + c0);
+                    y0 = ld_sh(src + DD + c0);
+                    z0 = ld_sh(src + 2 * DD + c0);
                 }
                 if (j1 < D) {
                     const int c1 = j1 * D + i;
-                    if (mask[c1]) {
-                        x1 = src[c1];
-                        y1 = src[DD + c1];
-                        z1 = src[2 * DD + c1];
+                    if (in_disk(j1, i, D)) {
+                        x1 = ld_sh(src + c1);
+                        y1 = ld_sh(src + DD + c1);
+                        z1 = ld_sh(src + 2 * DD + c1);
                     }
                 }
             }
@@ -103,9 +112,9 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                                           0.5f * (A1.y + B1.y), -0.5f * (A1.x - B1.x));
             const float4 sz = make_float4(0.5f * (A2.x + B2.x), 0.5f * (A2.y - B2.y),
                                           0.5f * (A2.y + B2.y), -0.5f * (A2.x - B2.x));
-            *reinterpret_cast<float4*>(S + (size_t)(0 * H + k) * Dp + j0) = sx;
-            *reinterpret_cast<float4*>(S + (size_t)(1 * H + k) * Dp + j0) = sy;
-            *reinterpret_cast<float4*>(S + (size_t)(2 * H + k) * Dp + j0) = sz;
+            st_sh4(S + (size_t)(0 * H + k) * Dp + j0, sx);
+            st_sh4(S + (size_t)(1 * H + k) * Dp + j0, sy);
+            st_sh4(S + (size_t)(2 * H + k) * Dp + j0, sz);
         }
         __syncthreads();
     };
@@ -119,7 +128,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const int i = t + j * Tf;
-            v[j] = (valid && i < D) ? col[i] : make_float2(0.f, 0.f);
+            v[j] = (valid && i < D) ? ld_sh2(col + i) : make_float2(0.f, 0.f);
         }
         fft_run<P, R, false>(v, mybuf, ltw, t);
         for (int idx = threadIdx.x; idx < U * P; idx += NT) {
@@ -141,7 +150,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         for (int j = 0; j < R; ++j) v[j] = mybuf[t + j * Tf];
         fft_run<P, R, true>(v, mybuf, ltw, t);
         if (valid)
-            for (int i = t; i < D; i += Tf) col[i] = mybuf[i];
+            for (int i = t; i < D; i += Tf) st_sh2(col + i, mybuf[i]);
         __syncthreads();
     };
 
@@ -153,9 +162,9 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             float4 sx = make_float4(0.f, 0.f, 0.f, 0.f), sy = sx, sz = sx;
             if (p < d.n_pairs) {
                 const int j0 = 2 * p;
-                sx = *reinterpret_cast<const float4*>(S + (size_t)(0 * H + k) * Dp + j0);
-                sy = *reinterpret_cast<const float4*>(S + (size_t)(1 * H + k) * Dp + j0);
-                sz = *reinterpret_cast<const float4*>(S + (size_t)(2 * H + k) * Dp + j0);
+                sx = ld_sh4(S + (size_t)(0 * H + k) * Dp + j0);
+                sy = ld_sh4(S + (size_t)(1 * H + k) * Dp + j0);
+                sz = ld_sh4(S + (size_t)(2 * H + k) * Dp + j0);
             }
             // Hx + i Hy of each row, Hz(j0) + i Hz(j1); mirrored half from Hermitian symmetry
             BUF(0, uu)[k] = make_float2(sx.x - sy.y, sx.y + sy.x);
@@ -179,150 +188,155 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     const float hxf = pr.hx, hyf = pr.hy, hzf = pr.hz, cf = pr.c, al = pr.alpha, dt = pr.dtau;
 
     // ---- per-cell work after the inverse transforms; new stage state back into LDS
-    // stage s of step n; Ys = state whose field is in LDS; Yn = where the next stage state goes
+    // stage s of step n; Ys = state whose field is in LDS; Yn = where the next stage state goes.
+    // Every global value a column of the row pair needs is gathered first with
+    // independent loads (one memory latency), then both cells are updated.
+    const bool need_y0 = (mode == MODE_RK4) || (mode == MODE_HEUN);
     auto cell_update = [&](int b, int s, long long n, const float* Ys, float* Yn) {
+        const bool need_acc = (mode == MODE_RK4 && s > 0) || (mode == MODE_HEUN && s == 1);
         for (int idx = threadIdx.x; idx < U * D; idx += NT) {
             const int uu = idx / D, i = idx - uu * D;
             const int p = b * U + uu;
             if (p >= d.n_pairs) continue;
-            const float2 hz2 = BUF(2, uu)[i];
-            float2 nz2 = make_float2(0.f, 0.f);
+            const int j0 = 2 * p;
+            float col[4][3], lft[2][3], rgt[2][3], y0[2][3], ac[2][3];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = j0 - 1 + r;
+                const bool ok = j >= 0 && j < D && in_disk(j, i, D);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) col[r][c] = ok ? ld_sh(Ys + c * DD + j * D + i) : 0.f;
+            }
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
-                const int j = 2 * p + r;
+                const int j = j0 + r;
+                const bool okl = j < D && i > 0 && in_disk(j, i - 1, D);
+                const bool okr = j < D && i + 1 < D && in_disk(j, i + 1, D);
+                const bool okc = j < D && in_disk(j, i, D);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int cell = c * DD + j * D + i;
+                    lft[r][c] = okl ? ld_sh(Ys + cell - 1) : 0.f;
+                    rgt[r][c] = okr ? ld_sh(Ys + cell + 1) : 0.f;
+                    y0[r][c] = (need_y0 && okc) ? ld_sh(m + cell) : 0.f;
+                    ac[r][c] = (need_acc && okc) ? d.acc[cell] : 0.f;
+                }
+            }
+            const float2 hz2 = BUF(2, uu)[i];
+            float nxt[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int j = j0 + r;
                 if (j >= D) break;
+                const int cell = j * D + i;
+                const bool in = in_disk(j, i, D);
                 const float2 hxy = BUF(r, uu)[i];
                 const float Hx = hxy.x, Hy = hxy.y, Hz = r == 0 ? hz2.x : hz2.y;
-                const int cell = j * D + i;
-                float nx = 0.f, ny = 0.f, nzv = 0.f;
-                if (mask[cell]) {
-                    const float mx = Ys[cell], my = Ys[DD + cell], mz = Ys[2 * DD + cell];
-                    float ex = 0.f, ey = 0.f, ez = 0.f;
-                    double exd = 0.0, eyd = 0.0, ezd = 0.0;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int jj = j + (q == 0 ? -1 : q == 1 ? 1 : 0);
-                        const int ii = i + (q == 2 ? -1 : q == 3 ? 1 : 0);
-                        if (jj < 0 || jj >= D || ii < 0 || ii >= D) continue;
-                        const int cn = jj * D + ii;
-                        if (!mask[cn]) continue;
-                        const float vx = Ys[cn], vy = Ys[DD + cn], vz = Ys[2 * DD + cn];
-                        if (mode == MODE_ENERGY) {
-                            exd += vx;
-                            eyd += vy;
-                            ezd += vz;
-                        } else {
-                            ex += vx;
-                            ey += vy;
-                            ez += vz;
-                        }
-                    }
-                    if (mode == MODE_DEMAG) {
-                        out[cell] = Hx;
-                        out[DD + cell] = Hy;
-                        out[2 * DD + cell] = Hz;
-                        continue;
-                    }
-                    if (mode == MODE_ENERGY) {
-                        const double mxd = mx, myd = my, mzd = mz;
-                        e_ex += -0.5 * (mxd * exd + myd * eyd + mzd * ezd);
-                        e_dm += -0.5 * pr.c_d * (mxd * (double)Hx + myd * (double)Hy + mzd * (double)Hz);
-                        e_ext += -pr.c_d * (mxd * pr.hx_d + myd * pr.hy_d + mzd * pr.hz_d);
-                        continue;
-                    }
-                    const float bx = ex + cf * (hxf + Hx);
-                    const float by = ey + cf * (hyf + Hy);
-                    const float bz = ez + cf * (hzf + Hz);
-                    if (mode == MODE_RHS || mode == MODE_RK4) {
-                        // f = m x b - alpha m x (m x b)
-                        const float px = my * bz - mz * by, py = mz * bx - mx * bz, pz = mx * by - my * bx;
-                        const float fx = px - al * (my * pz - mz * py);
-                        const float fy = py - al * (mz * px - mx * pz);
-                        const float fz = pz - al * (mx * py - my * px);
-                        if (mode == MODE_RHS) {
-                            out[cell] = fx;
-                            out[DD + cell] = fy;
-                            out[2 * DD + cell] = fz;
-                            continue;
-                        }
-                        const float y0x = m[cell], y0y = m[DD + cell], y0z = m[2 * DD + cell];
-                        if (s == 0) {
-                            d.acc[cell] = fx;
-                            d.acc[DD + cell] = fy;
-                            d.acc[2 * DD + cell] = fz;
-                        } else if (s < 3) {
-                            d.acc[cell] += 2.f * fx;
-                            d.acc[DD + cell] += 2.f * fy;
-                            d.acc[2 * DD + cell] += 2.f * fz;
-                        }
-                        if (s < 3) {
-                            const float h = (s == 2) ? dt : 0.5f * dt;
-                            nx = y0x + h * fx;
-                            ny = y0y + h * fy;
-                            nzv = y0z + h * fz;
-                        } else {
-                            const float h6 = dt * (1.0f / 6.0f);
-                            nx = y0x + h6 * (d.acc[cell] + fx);
-                            ny = y0y + h6 * (d.acc[DD + cell] + fy);
-                            nzv = y0z + h6 * (d.acc[2 * DD + cell] + fz);
-                            if (pr.renorm) {
-                                const float rn = 1.0f / sqrtf(nx * nx + ny * ny + nzv * nzv);
-                                nx *= rn;
-                                ny *= rn;
-                                nzv *= rn;
-                            }
-                            if (!(isfinite(nx) && isfinite(ny) && isfinite(nzv)))
-                                __hip_atomic_fetch_or(a.err, (int)ERR_NONFINITE, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
-                        }
-                    } else {  // MODE_HEUN
-                        const float3 w = thermal_normals(a.seed, a.step0 + (unsigned long long)n,
-                                                         (unsigned long long)cell,
-                                                         (unsigned long long)(a.replica0 + d.k));
-                        const float sg = pr.sigma;
-                        const float gx = bx * dt + sg * w.x, gy = by * dt + sg * w.y, gz = bz * dt + sg * w.z;
-                        const float px = my * gz - mz * gy, py = mz * gx - mx * gz, pz = mx * gy - my * gx;
-                        const float dx = px - al * (my * pz - mz * py);
-                        const float dy = py - al * (mz * px - mx * pz);
-                        const float dz = pz - al * (mx * py - my * px);
-                        if (s == 0) {
-                            d.acc[cell] = dx;
-                            d.acc[DD + cell] = dy;
-                            d.acc[2 * DD + cell] = dz;
-                            nx = mx + dx;
-                            ny = my + dy;
-                            nzv = mz + dz;
-                        } else {
-                            nx = m[cell] + 0.5f * (d.acc[cell] + dx);
-                            ny = m[DD + cell] + 0.5f * (d.acc[DD + cell] + dy);
-                            nzv = m[2 * DD + cell] + 0.5f * (d.acc[2 * DD + cell] + dz);
-                            if (pr.renorm) {
-                                const float rn = 1.0f / sqrtf(nx * nx + ny * ny + nzv * nzv);
-                                nx *= rn;
-                                ny *= rn;
-                                nzv *= rn;
-                            }
-                            if (!(isfinite(nx) && isfinite(ny) && isfinite(nzv)))
-                                __hip_atomic_fetch_or(a.err, (int)ERR_NONFINITE, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
-                        }
-                    }
-                } else if (mode == MODE_DEMAG || mode == MODE_RHS) {
-                    out[cell] = 0.f;
-                    out[DD + cell] = 0.f;
-                    out[2 * DD + cell] = 0.f;
-                    continue;
-                } else if (mode == MODE_ENERGY) {
+                if (mode == MODE_DEMAG) {
+                    out[cell] = in ? Hx : 0.f;
+                    out[DD + cell] = in ? Hy : 0.f;
+                    out[2 * DD + cell] = in ? Hz : 0.f;
                     continue;
                 }
+                const float mx = col[r + 1][0], my = col[r + 1][1], mz = col[r + 1][2];
+                if (mode == MODE_ENERGY) {
+                    if (!in) continue;
+                    double e3[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        e3[c] = (double)col[r][c] + (double)col[r + 2][c] + (double)lft[r][c] + (double)rgt[r][c];
+                    const double mxd = mx, myd = my, mzd = mz;
+                    e_ex += -0.5 * (mxd * e3[0] + myd * e3[1] + mzd * e3[2]);
+                    e_dm += -0.5 * pr.c_d * (mxd * (double)Hx + myd * (double)Hy + mzd * (double)Hz);
+                    e_ext += -pr.c_d * (mxd * pr.hx_d + myd * pr.hy_d + mzd * pr.hz_d);
+                    continue;
+                }
+                const float bx = (col[r][0] + col[r + 2][0] + lft[r][0] + rgt[r][0]) + cf * (hxf + Hx);
+                const float by = (col[r][1] + col[r + 2][1] + lft[r][1] + rgt[r][1]) + cf * (hyf + Hy);
+                const float bz = (col[r][2] + col[r + 2][2] + lft[r][2] + rgt[r][2]) + cf * (hzf + Hz);
+                float nx = 0.f, ny = 0.f, nzv = 0.f;
+                if (mode == MODE_RHS || mode == MODE_RK4) {
+                    // f = m x b - alpha m x (m x b)
+                    const float px = my * bz - mz * by, py = mz * bx - mx * bz, pz = mx * by - my * bx;
+                    const float fx = px - al * (my * pz - mz * py);
+                    const float fy = py - al * (mz * px - mx * pz);
+                    const float fz = pz - al * (mx * py - my * px);
+                    if (mode == MODE_RHS) {
+                        out[cell] = in ? fx : 0.f;
+                        out[DD + cell] = in ? fy : 0.f;
+                        out[2 * DD + cell] = in ? fz : 0.f;
+                        continue;
+                    }
+                    if (in) {
+                        if (s < 3) {
+                            const float w = (s == 0) ? 1.f : 2.f;
+                            d.acc[cell] = ac[r][0] + w * fx;
+                            d.acc[DD + cell] = ac[r][1] + w * fy;
+                            d.acc[2 * DD + cell] = ac[r][2] + w * fz;
+                            const float h = (s == 2) ? dt : 0.5f * dt;
+                            nx = y0[r][0] + h * fx;
+                            ny = y0[r][1] + h * fy;
+                            nzv = y0[r][2] + h * fz;
+                        } else {
+                            const float h6 = dt * (1.0f / 6.0f);
+                            nx = y0[r][0] + h6 * (ac[r][0] + fx);
+                            ny = y0[r][1] + h6 * (ac[r][1] + fy);
+                            nzv = y0[r][2] + h6 * (ac[r][2] + fz);
+                            if (pr.renorm) {
+                                const float rn = 1.0f / sqrtf(nx * nx + ny * ny + nzv * nzv);
+                                nx *= rn;
+                                ny *= rn;
+                                nzv *= rn;
+                            }
+                            if (!(isfinite(nx) && isfinite(ny) && isfinite(nzv)))
+                                __hip_atomic_fetch_or(a.err, (int)ERR_NONFINITE, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                    }
+                } else if (in) {  // MODE_HEUN
+                    const float3 w = thermal_normals(a.seed, a.step0 + (unsigned long long)n, (unsigned long long)cell,
+                                                     (unsigned long long)(a.replica0 + d.k));
+                    const float sg = pr.sigma;
+                    const float gx = bx * dt + sg * w.x, gy = by * dt + sg * w.y, gz = bz * dt + sg * w.z;
+                    const float px = my * gz - mz * gy, py = mz * gx - mx * gz, pz = mx * gy - my * gx;
+                    const float dx = px - al * (my * pz - mz * py);
+                    const float dy = py - al * (mz * px - mx * pz);
+                    const float dz = pz - al * (mx * py - my * px);
+                    if (s == 0) {
+                        d.acc[cell] = dx;
+                        d.acc[DD + cell] = dy;
+                        d.acc[2 * DD + cell] = dz;
+                        nx = mx + dx;
+                        ny = my + dy;
+                        nzv = mz + dz;
+                    } else {
+                        nx = y0[r][0] + 0.5f * (ac[r][0] + dx);
+                        ny = y0[r][1] + 0.5f * (ac[r][1] + dy);
+                        nzv = y0[r][2] + 0.5f * (ac[r][2] + dz);
+                        if (pr.renorm) {
+                            const float rn = 1.0f / sqrtf(nx * nx + ny * ny + nzv * nzv);
+                            nx *= rn;
+                            ny *= rn;
+                            nzv *= rn;
+                        }
+                        if (!(isfinite(nx) && isfinite(ny) && isfinite(nzv)))
+                            __hip_atomic_fetch_or(a.err, (int)ERR_NONFINITE, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
                 // integrators: store the next stage state (zero outside the disk)
-                Yn[cell] = nx;
-                Yn[DD + cell] = ny;
-                Yn[2 * DD + cell] = nzv;
-                BUF(r, uu)[i] = make_float2(nx, ny);
-                if (r == 0) nz2.x = nzv; else nz2.y = nzv;
+                st_sh(Yn + cell, nx);
+                st_sh(Yn + DD + cell, ny);
+                st_sh(Yn + 2 * DD + cell, nzv);
+                nxt[r][0] = nx;
+                nxt[r][1] = ny;
+                nxt[r][2] = nzv;
             }
-            if (mode == MODE_RK4 || mode == MODE_HEUN) BUF(2, uu)[i] = nz2;
+            if (mode == MODE_RK4 || mode == MODE_HEUN) {
+                BUF(0, uu)[i] = make_float2(nxt[0][0], nxt[0][1]);
+                BUF(1, uu)[i] = make_float2(nxt[1][0], nxt[1][1]);
+                BUF(2, uu)[i] = make_float2(nxt[0][2], nxt[1][2]);
+            }
         }
         __syncthreads();
     };
