@@ -145,6 +145,33 @@ int llg_heun_step(llg_disk h, float* m, long long nsteps, unsigned long long see
                   unsigned long long step0, unsigned int replica, const llg_params* p,
                   void* stream);
 
+/* Adjoint support (the paper integrates forward only; this is the hand-written
+ * reverse mode of its RK4 step, Sec. III.A).
+ *
+ * llg_rk4_record: nsteps RK4 steps in place like llg_rk4_step (renorm must be
+ * off) that also store, for every step n and stage s, the stage state and its
+ * demag field into rec: disk k's block starts at float offset
+ * 8 * nsteps * llg_disk_offset(h, k) and holds [nsteps][4][2][3][D][D]
+ * (stage state, demag field).  rec needs 8 * nsteps * llg_state_size(h) floats.
+ *
+ * llg_rk4_vjp: reverse pass over the same nsteps: on entry ybar holds the
+ * cotangent of the state after the last step, on exit the cotangent of the
+ * state before the first step.  pgrad (2 doubles per disk) is incremented by
+ * d/d alpha and d/d c of the same scalar.  The demag and exchange operators are
+ * symmetric, so the reverse pass applies the forward field machinery to the
+ * cotangent of the induction at every stage.  rec must come from
+ * llg_rk4_record with the same nsteps and params. */
+int llg_rk4_record(llg_disk h, float* m, long long nsteps, const llg_params* p, float* rec, void* stream);
+int llg_rk4_vjp(llg_disk h, const float* rec, long long nsteps, float* ybar, double* pgrad,
+                const llg_params* p, void* stream);
+
+/* Cotangent of the core position: with the plaquette r_v and the cutoff set
+ * frozen at `core` (the out array llg_vortex_core_position returned for the
+ * same m), adds d(rbar . r_c)/dm to mbar (packed like m).  rbar: 2 doubles per
+ * disk (device), in 1/nm. */
+int llg_core_position_vjp(llg_disk h, const float* m, double lambda_ex_nm, const double* core,
+                          const double* rbar, float* mbar, void* stream);
+
 /* The noise w that llg_heun_step uses at one time step (test hook), packed
  * like m (zero outside the disks). */
 int llg_noise(llg_disk h, unsigned long long seed, unsigned long long step,

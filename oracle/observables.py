@@ -114,3 +114,20 @@ def vortex_core_position(m: torch.Tensor, disk: Disk, lambda_ex_nm: float, hint_
     xc = float((w * x).sum() / ws) * a
     yc = float((w * y).sum() / ws) * a
     return xc, yc, xv * a, yv * a, n_plus
+
+
+def core_centroid(m: torch.Tensor, disk: Disk, lambda_ex_nm: float, xv_nm: float, yv_nm: float,
+                  found: bool = True) -> torch.Tensor:
+    """r_c (nm) as a differentiable function of m with the plaquette r_v and the
+    cutoff set held fixed (the smooth part of the core-position definition);
+    used to differentiate trajectory losses."""
+    a = disk.a_nm
+    mz2 = disk.apply_mask(m)[2] ** 2
+    if found:
+        cutoff = 4.0 * lambda_ex_nm / a
+        near = ((disk.x - xv_nm / a) ** 2 + (disk.y - yv_nm / a) ** 2 < cutoff * cutoff) & disk.mask
+    else:
+        near = disk.mask
+    w = mz2 * near.to(m.dtype)
+    ws = w.sum()
+    return torch.stack([(w * disk.x).sum() / ws * a, (w * disk.y).sum() / ws * a])

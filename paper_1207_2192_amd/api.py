@@ -170,6 +170,31 @@ class Disk:
                                         self._params(params), _stream()), "llg_heun_step")
         return m
 
+    def rk4_record(self, m: torch.Tensor, nsteps: int, params, rec: torch.Tensor) -> torch.Tensor:
+        m = self._state(m)
+        if rec.dtype != torch.float32 or rec.device.type != "cuda" or rec.numel() < 8 * nsteps * self.state_size:
+            raise ValueError("rec must be a float32 CUDA tensor of 8 * nsteps * state_size elements")
+        check(_lib.load().llg_rk4_record(self._h, _ptr(m), int(nsteps), self._params(params), _ptr(rec), _stream()),
+              "llg_rk4_record")
+        return m
+
+    def rk4_vjp(self, rec: torch.Tensor, nsteps: int, ybar: torch.Tensor, pgrad: torch.Tensor, params):
+        ybar = self._state(ybar, "ybar")
+        if pgrad.dtype != torch.float64 or pgrad.numel() != 2 * self.n or pgrad.device.type != "cuda":
+            raise ValueError("pgrad must be a float64 CUDA tensor with 2 entries per disk")
+        check(_lib.load().llg_rk4_vjp(self._h, _ptr(rec), int(nsteps), _ptr(ybar), _ptr(pgrad),
+                                      self._params(params), _stream()), "llg_rk4_vjp")
+        return ybar
+
+    def core_position_vjp(self, m: torch.Tensor, lambda_ex_nm: float, core: torch.Tensor, rbar: torch.Tensor,
+                          mbar: torch.Tensor):
+        m = self._state(m)
+        mbar = self._state(mbar, "mbar")
+        check(_lib.load().llg_core_position_vjp(self._h, _ptr(m), float(lambda_ex_nm), _ptr(core.contiguous()),
+                                                _ptr(rbar.contiguous()), _ptr(mbar), _stream()),
+              "llg_core_position_vjp")
+        return mbar
+
     def noise(self, seed: int, step: int, replica: int = 0) -> torch.Tensor:
         w = torch.empty(self.state_size, dtype=torch.float32, device=self.device)
         check(_lib.load().llg_noise(self._h, int(seed), int(step), int(replica), _ptr(w), _stream()), "llg_noise")

@@ -21,7 +21,8 @@ struct DiskDesc {
     long long m_off;          // float offset of this disk in a packed state
     float* ya;                // stage state A  [3][D][D]
     float* yb;                // stage state B  [3][D][D]
-    float* acc;               // RK4 accumulator / Heun predictor increment [3][D][D]
+    float* acc;               // RK4 accumulator / Heun predictor increment / adjoint accumulator [3][D][D]
+    float* aux;               // adjoint: direct part of the stage cotangent [3][D][D]
     float2* S;                // row/column spectra [3][H][Dp]
     const float* spec;        // kernel spectra quarter planes [4][H][H] (xx, yy, xy, zz) / P^2
     const unsigned char* mask;  // [D][D]
@@ -37,7 +38,7 @@ struct DiskPrm {
     double c_d, hx_d, hy_d, hz_d;
 };
 
-enum Mode : int { MODE_DEMAG = 0, MODE_RHS = 1, MODE_ENERGY = 2, MODE_RK4 = 3, MODE_HEUN = 4 };
+enum Mode : int { MODE_DEMAG = 0, MODE_RHS = 1, MODE_ENERGY = 2, MODE_RK4 = 3, MODE_HEUN = 4, MODE_RK4_VJP = 5 };
 
 enum ErrBits : int { ERR_BARRIER = 1, ERR_NONFINITE = 2 };
 
@@ -48,6 +49,7 @@ struct KArgs {
     const int* wg2local;
     float* m;             // packed state (input, or in/out for the integrators)
     float* out;           // packed output (demag field or rhs), may be null
+    float* rec;           // RK4 stage record (stage states and demag fields), may be null
     long long nsteps;
     unsigned long long seed, step0;
     unsigned int replica0;

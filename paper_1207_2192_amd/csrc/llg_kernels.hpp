@@ -192,6 +192,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     // Every global value a column of the row pair needs is gathered first with
     // independent loads (one memory latency), then both cells are updated.
     const bool need_y0 = (mode == MODE_RK4) || (mode == MODE_HEUN);
+    float* const recd = a.rec ? a.rec + (size_t)a.nsteps * 8 * (size_t)d.m_off : nullptr;
     auto cell_update = [&](int b, int s, long long n, const float* Ys, float* Yn) {
         const bool need_acc = (mode == MODE_RK4 && s > 0) || (mode == MODE_HEUN && s == 1);
         for (int idx = threadIdx.x; idx < U * D; idx += NT) {
@@ -267,6 +268,15 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                         out[2 * DD + cell] = in ? fz : 0.f;
                         continue;
                     }
+                    if (recd) {
+                        float* rs = recd + ((size_t)(n * 4 + s) * 2) * 3 * DD + cell;
+                        rs[0] = in ? mx : 0.f;
+                        rs[DD] = in ? my : 0.f;
+                        rs[2 * DD] = in ? mz : 0.f;
+                        rs[3 * DD] = in ? Hx : 0.f;
+                        rs[4 * DD] = in ? Hy : 0.f;
+                        rs[5 * DD] = in ? Hz : 0.f;
+                    }
                     if (in) {
                         if (s < 3) {
                             const float w = (s == 0) ? 1.f : 2.f;
@@ -341,7 +351,188 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         __syncthreads();
     };
 
+    // ---- adjoint of RK4 (backward stage k finishes stage k-1 and starts stage k)
+    // Backward stage k <-> step n = N-1-k/4, forward stage s = 3-k%4.  With the
+    // recorded stage state Y and demag field H of that stage, the cotangent kb of
+    // the stage slope gives (b = exchange(Y) + c (h + H)):
+    //   direct part  mdir = b x kb - alpha [(Y x b) x kb + b x (kb x Y)]
+    //   field part   bbar = kb x Y - alpha (kb x Y) x Y
+    //   stage cotangent  Ybar = mdir + exchange(bbar) + c K bbar   (K: demag, self-adjoint)
+    //   alpha_bar += kb . (-Y x (Y x b)),   c_bar += bbar . (h + H).
+    // The slope cotangents follow RK4 backwards: kb_4 = dt/6 yb', kb_3 = dt/3 yb' + dt Ybar_4,
+    // kb_2 = dt/3 yb' + dt/2 Ybar_3, kb_1 = dt/6 yb' + dt/2 Ybar_2;  yb = yb' + sum Ybar.
+    auto vjp_update = [&](int b, long long k, long long K) {
+        const long long N = a.nsteps;
+        const bool fin = k > 0, sta = k < K;
+        const long long nf = fin ? N - 1 - (k - 1) / 4 : 0, ns = sta ? N - 1 - k / 4 : 0;
+        const int sf = fin ? 3 - (int)((k - 1) % 4) : 0, ss = sta ? 3 - (int)(k % 4) : 0;
+        const float* Bf = ((k - 1) & 1) ? d.yb : d.ya;      // bbar of the finishing stage
+        float* Bs = (k & 1) ? d.yb : d.ya;                  // bbar of the starting stage
+        const float* Yrec = recd + ((size_t)(ns * 4 + ss) * 2) * 3 * DD;
+        const float* Hrec = Yrec + 3 * DD;
+        const float* Hfin = recd + ((size_t)(nf * 4 + sf) * 2 + 1) * 3 * DD;
+        for (int idx = threadIdx.x; idx < U * D; idx += NT) {
+            const int uu = idx / D, i = idx - uu * D;
+            const int p = b * U + uu;
+            if (p >= d.n_pairs) continue;
+            const int j0 = 2 * p;
+            float bc[4][3], bl[2][3], br[2][3], yc[4][3], yl[2][3], yr[2][3];
+            float ax[2][3], ac[2][3], hf[2][3], hs[2][3], yb0[2][3];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = j0 - 1 + r;
+                const bool ok = j >= 0 && j < D && in_disk(j, i, D);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    bc[r][c] = (fin && ok) ? ld_sh(Bf + c * DD + j * D + i) : 0.f;
+                    yc[r][c] = (sta && ok) ? Yrec[c * DD + j * D + i] : 0.f;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int j = j0 + r;
+                const bool okl = j < D && i > 0 && in_disk(j, i - 1, D);
+                const bool okr = j < D && i + 1 < D && in_disk(j, i + 1, D);
+                const bool okc = j < D && in_disk(j, i, D);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int cell = c * DD + j * D + i;
+                    bl[r][c] = (fin && okl) ? ld_sh(Bf + cell - 1) : 0.f;
+                    br[r][c] = (fin && okr) ? ld_sh(Bf + cell + 1) : 0.f;
+                    yl[r][c] = (sta && okl) ? Yrec[cell - 1] : 0.f;
+                    yr[r][c] = (sta && okr) ? Yrec[cell + 1] : 0.f;
+                    ax[r][c] = (fin && okc) ? d.aux[cell] : 0.f;
+                    ac[r][c] = (fin && okc) ? d.acc[cell] : 0.f;
+                    hf[r][c] = (fin && okc) ? Hfin[cell] : 0.f;
+                    hs[r][c] = (sta && okc) ? Hrec[cell] : 0.f;
+                    yb0[r][c] = (sta && okc) ? ld_sh(m + cell) : 0.f;
+                }
+            }
+            const float2 hz2 = BUF(2, uu)[i];
+            float nxt[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int j = j0 + r;
+                if (j >= D) break;
+                const int cell = j * D + i;
+                if (!in_disk(j, i, D)) {
+                    if (sta) {
+                        st_sh(Bs + cell, 0.f);
+                        st_sh(Bs + DD + cell, 0.f);
+                        st_sh(Bs + 2 * DD + cell, 0.f);
+                    }
+                    continue;
+                }
+                float yprev[3] = {0.f, 0.f, 0.f};
+                float ybar[3] = {yb0[r][0], yb0[r][1], yb0[r][2]};
+                if (fin) {
+                    const float2 kxy = BUF(r, uu)[i];
+                    const float Kb[3] = {kxy.x, kxy.y, r == 0 ? hz2.x : hz2.y};
+                    float accn[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const float ex = bc[r][c] + bc[r + 2][c] + bl[r][c] + br[r][c];
+                        yprev[c] = ax[r][c] + ex + cf * Kb[c];
+                        accn[c] = ac[r][c] + yprev[c];
+                    }
+                    const float hh[3] = {hxf, hyf, hzf};
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) e_dm += (double)bc[r + 1][c] * ((double)hh[c] + (double)hf[r][c]);
+                    if (sf == 0) {  // step nf complete: yb_nf = accumulated cotangent
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            st_sh(m + c * DD + cell, accn[c]);
+                            ybar[c] = accn[c];
+                        }
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) d.acc[c * DD + cell] = accn[c];
+                    }
+                }
+                if (sta) {
+                    if (ss == 3) {
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) d.acc[c * DD + cell] = ybar[c];
+                    }
+                    const float w = (ss == 3 || ss == 0) ? dt * (1.0f / 6.0f) : dt * (1.0f / 3.0f);
+                    const float v = (ss == 3) ? 0.f : (ss == 2) ? dt : 0.5f * dt;
+                    const float kx = w * ybar[0] + v * yprev[0];
+                    const float ky = w * ybar[1] + v * yprev[1];
+                    const float kz = w * ybar[2] + v * yprev[2];
+                    const float Yx = yc[r + 1][0], Yy = yc[r + 1][1], Yz = yc[r + 1][2];
+                    const float bx = (yc[r][0] + yc[r + 2][0] + yl[r][0] + yr[r][0]) + cf * (hxf + hs[r][0]);
+                    const float by = (yc[r][1] + yc[r + 2][1] + yl[r][1] + yr[r][1]) + cf * (hyf + hs[r][1]);
+                    const float bz = (yc[r][2] + yc[r + 2][2] + yl[r][2] + yr[r][2]) + cf * (hzf + hs[r][2]);
+                    // Y x b
+                    const float px = Yy * bz - Yz * by, py = Yz * bx - Yx * bz, pz = Yx * by - Yy * bx;
+                    // kb x Y
+                    const float qx = ky * Yz - kz * Yy, qy = kz * Yx - kx * Yz, qz = kx * Yy - ky * Yx;
+                    // mdir = b x kb - alpha [ (Y x b) x kb + b x (kb x Y) ]
+                    const float m1x = by * kz - bz * ky, m1y = bz * kx - bx * kz, m1z = bx * ky - by * kx;
+                    const float m2x = py * kz - pz * ky, m2y = pz * kx - px * kz, m2z = px * ky - py * kx;
+                    const float m3x = by * qz - bz * qy, m3y = bz * qx - bx * qz, m3z = bx * qy - by * qx;
+                    d.aux[cell] = m1x - al * (m2x + m3x);
+                    d.aux[DD + cell] = m1y - al * (m2y + m3y);
+                    d.aux[2 * DD + cell] = m1z - al * (m2z + m3z);
+                    // bbar = kb x Y - alpha (kb x Y) x Y
+                    const float gx = qx - al * (qy * Yz - qz * Yy);
+                    const float gy = qy - al * (qz * Yx - qx * Yz);
+                    const float gz = qz - al * (qx * Yy - qy * Yx);
+                    st_sh(Bs + cell, gx);
+                    st_sh(Bs + DD + cell, gy);
+                    st_sh(Bs + 2 * DD + cell, gz);
+                    // alpha_bar += kb . ( -Y x (Y x b) )
+                    const float tx = Yy * pz - Yz * py, ty = Yz * px - Yx * pz, tz = Yx * py - Yy * px;
+                    e_ex += -((double)kx * tx + (double)ky * ty + (double)kz * tz);
+                    nxt[r][0] = gx;
+                    nxt[r][1] = gy;
+                    nxt[r][2] = gz;
+                }
+            }
+            if (sta) {
+                BUF(0, uu)[i] = make_float2(nxt[0][0], nxt[0][1]);
+                BUF(1, uu)[i] = make_float2(nxt[1][0], nxt[1][1]);
+                BUF(2, uu)[i] = make_float2(nxt[0][2], nxt[1][2]);
+            }
+        }
+        __syncthreads();
+    };
+
+    auto write_partials = [&](double s0v, double s1v, double s2v) {
+        __shared__ double red[3 * MAX_UG][3];
+        const double s0 = wave_sum(s0v), s1 = wave_sum(s1v), s2 = wave_sum(s2v);
+        if (lane == 0) {
+            red[wv][0] = s0;
+            red[wv][1] = s1;
+            red[wv][2] = s2;
+        }
+        __syncthreads();
+        if (threadIdx.x < 3) {
+            const int q = threadIdx.x;
+            double acc = 0.0;
+            for (int w = 0; w < 3 * UG; ++w) acc += red[w][q];
+            d.part[g * 4 + q] = acc;
+        }
+    };
+
     // ---------------------------------------------------------------- program
+    if (mode == MODE_RK4_VJP) {
+        const long long K = 4 * a.nsteps;
+        for (long long k = 0; k <= K; ++k) {
+            for (int b = g; b < n_rb; b += G) {
+                if (k > 0) row_inverse(b);
+                vjp_update(b, k, K);
+                if (k < K) row_forward_store(b);
+            }
+            if (k == K) break;
+            if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
+            for (int b = g; b < n_cb; b += G) column_phase(b);
+            if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
+        }
+        write_partials(e_ex, e_dm, 0.0);
+        return;
+    }
+
     for (int b = g; b < n_rb; b += G) {
         load_state_rows(b, m);
         row_forward_store(b);
@@ -355,22 +546,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             row_inverse(b);
             cell_update(b, 0, 0, m, nullptr);
         }
-        if (mode == MODE_ENERGY) {
-            __shared__ double red[3 * MAX_UG][3];
-            const double s0 = wave_sum(e_ex), s1 = wave_sum(e_dm), s2 = wave_sum(e_ext);
-            if (lane == 0) {
-                red[wv][0] = s0;
-                red[wv][1] = s1;
-                red[wv][2] = s2;
-            }
-            __syncthreads();
-            if (threadIdx.x < 3) {
-                const int q = threadIdx.x;
-                double acc = 0.0;
-                for (int w = 0; w < 3 * UG; ++w) acc += red[w][q];
-                d.part[g * 4 + q] = acc;
-            }
-        }
+        if (mode == MODE_ENERGY) write_partials(e_ex, e_dm, e_ext);
         return;
     }
 
@@ -440,6 +616,21 @@ __global__ void energy_finalize(const DiskDesc* disks, int n, double* out) {
     out[4 * k + 1] = s0;
     out[4 * k + 2] = s1;
     out[4 * k + 3] = s2;
+}
+
+// Adjoint parameter gradients: pgrad[2k] += alpha_bar, pgrad[2k+1] += c_bar of disk k,
+// summed over the per-workgroup partials in workgroup order.
+__global__ void grad_finalize(const DiskDesc* disks, int n, double* pgrad) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const DiskDesc d = disks[k];
+    double s0 = 0.0, s1 = 0.0;
+    for (int g = 0; g < d.G; ++g) {
+        s0 += d.part[g * 4 + 0];
+        s1 += d.part[g * 4 + 1];
+    }
+    pgrad[2 * k] += s0;
+    pgrad[2 * k + 1] += s1;
 }
 
 // Noise field of one Heun step (test hook), packed like the state.
@@ -604,6 +795,52 @@ __global__ __launch_bounds__(OBS_THREADS) void core_kernel(const DiskDesc* disks
         out[5 * k + 2] = xv * a_nm;
         out[5 * k + 3] = yv * a_nm;
         out[5 * k + 4] = np;
+    }
+}
+
+// Cotangent of the core position r_c (Sec. IV) with the plaquette r_v and the
+// cutoff set frozen at the values of `core` (the output of core_kernel for the
+// same state): r_c = sum w_i r_i / W, w_i = m_z,i^2, so
+// dL/dm_z,i += 2 m_z,i (rbar . (r_i - r_c)) / W for cells of the set.
+// mbar is accumulated (packed like the state); positions in nm.
+__global__ __launch_bounds__(OBS_THREADS) void core_vjp_kernel(const DiskDesc* disks, const float* m_base,
+                                                               const double* core, const double* rbar, double a_nm,
+                                                               double cutoff_cells, float* mbar_base) {
+    __shared__ double sh[OBS_THREADS / 64];
+    const int k = blockIdx.x;
+    const DiskDesc d = disks[k];
+    const int D = d.D, DD = D * D;
+    const float* m = m_base + d.m_off;
+    float* mbar = mbar_base + d.m_off;
+    const double half = (D - 1) / 2.0;
+    const bool found = core[5 * k + 4] > 0.5;
+    const double xv = core[5 * k + 2] / a_nm, yv = core[5 * k + 3] / a_nm;
+    const double xc = core[5 * k + 0], yc = core[5 * k + 1];
+    const double rx = rbar[2 * k], ry = rbar[2 * k + 1];
+    const double c2 = cutoff_cells * cutoff_cells;
+    auto in_set = [&](int c, double& x, double& y) {
+        if (!d.mask[c]) return false;
+        const int j = c / D, i = c - j * D;
+        x = (double)i - half;
+        y = (double)j - half;
+        if (!found) return true;
+        const double ddx = x - xv, ddy = y - yv;
+        return ddx * ddx + ddy * ddy < c2;
+    };
+    double W = 0.0;
+    for (int c = threadIdx.x; c < DD; c += OBS_THREADS) {
+        double x, y;
+        if (!in_set(c, x, y)) continue;
+        const double z = m[2 * DD + c];
+        W += z * z;
+    }
+    W = block_sum(W, sh);
+    for (int c = threadIdx.x; c < DD; c += OBS_THREADS) {
+        double x, y;
+        if (!in_set(c, x, y)) continue;
+        const double z = m[2 * DD + c];
+        const double g = 2.0 * z * (rx * (x * a_nm - xc) + ry * (y * a_nm - yc)) / W;
+        mbar[2 * DD + c] += (float)g;
     }
 }
 

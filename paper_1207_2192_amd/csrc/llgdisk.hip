@@ -433,6 +433,7 @@ int create(int n, const double* R_nm, const double* L_nm, double a_nm, const int
         if ((rc = h->dalloc(&d.ya, 3 * DD))) return bail(rc);
         if ((rc = h->dalloc(&d.yb, 3 * DD))) return bail(rc);
         if ((rc = h->dalloc(&d.acc, 3 * DD))) return bail(rc);
+        if ((rc = h->dalloc(&d.aux, 3 * DD))) return bail(rc);
         if ((rc = h->dalloc(&d.S, (size_t)3 * d.H * d.Dp))) return bail(rc);
         HIP_TRY(hipMemset(d.S, 0, (size_t)3 * d.H * d.Dp * sizeof(float2)));
         d.spec = g.spec;
@@ -489,7 +490,7 @@ int upload_params(llg_disk h, const llg_params* p, hipStream_t st) {
 }
 
 int launch(llg_disk h, int mode, float* m, float* out, long long nsteps, unsigned long long seed,
-           unsigned long long step0, unsigned int replica0, hipStream_t st) {
+           unsigned long long step0, unsigned int replica0, hipStream_t st, float* rec = nullptr) {
     const int nb = (h->n_bars + 255) / 256;
     hipLaunchKernelGGL(zero_u32, dim3(nb), dim3(256), 0, st, h->bars, h->n_bars);
     HIP_TRY(hipGetLastError());
@@ -500,6 +501,7 @@ int launch(llg_disk h, int mode, float* m, float* out, long long nsteps, unsigne
     a.wg2local = h->wg2local;
     a.m = m;
     a.out = out;
+    a.rec = rec;
     a.nsteps = nsteps;
     a.seed = seed;
     a.step0 = step0;
@@ -612,6 +614,43 @@ int llg_rk4_step(llg_disk h, float* m, long long nsteps, const llg_params* p, vo
     if (nsteps == 0) return 0;
     if ((rc = upload_params(h, p, (hipStream_t)stream))) return rc;
     return launch(h, MODE_RK4, m, nullptr, nsteps, 0, 0, 0, (hipStream_t)stream);
+}
+
+int llg_rk4_record(llg_disk h, float* m, long long nsteps, const llg_params* p, float* rec, void* stream) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!m || !rec) return fail(LLG_EINVAL, "null array");
+    if (nsteps < 1) return fail(LLG_EINVAL, "nsteps < 1");
+    if ((rc = upload_params(h, p, (hipStream_t)stream))) return rc;
+    return launch(h, MODE_RK4, m, nullptr, nsteps, 0, 0, 0, (hipStream_t)stream, rec);
+}
+
+int llg_rk4_vjp(llg_disk h, const float* rec, long long nsteps, float* ybar, double* pgrad, const llg_params* p,
+                void* stream) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!rec || !ybar || !pgrad) return fail(LLG_EINVAL, "null array");
+    if (nsteps < 1) return fail(LLG_EINVAL, "nsteps < 1");
+    for (int k = 0; k < h->n; ++k)
+        if (p[k].renorm) return fail(LLG_EUNSUPPORTED, "the adjoint covers RK4 without renormalisation");
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = upload_params(h, p, st))) return rc;
+    if ((rc = launch(h, MODE_RK4_VJP, ybar, nullptr, nsteps, 0, 0, 0, st, const_cast<float*>(rec)))) return rc;
+    hipLaunchKernelGGL(grad_finalize, dim3((h->n + 63) / 64), dim3(64), 0, st, h->desc_dev, h->n, pgrad);
+    HIP_TRY(hipGetLastError());
+    return 0;
+}
+
+int llg_core_position_vjp(llg_disk h, const float* m, double lambda_ex_nm, const double* core, const double* rbar,
+                          float* mbar, void* stream) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!m || !core || !rbar || !mbar) return fail(LLG_EINVAL, "null array");
+    if (!(lambda_ex_nm > 0)) return fail(LLG_EINVAL, "lambda_ex must be positive");
+    hipLaunchKernelGGL(core_vjp_kernel, dim3(h->n), dim3(OBS_THREADS), 0, (hipStream_t)stream, h->desc_dev, m, core,
+                       rbar, h->a_nm, 4.0 * lambda_ex_nm / h->a_nm, mbar);
+    HIP_TRY(hipGetLastError());
+    return 0;
 }
 
 int llg_heun_step(llg_disk h, float* m, long long nsteps, unsigned long long seed, unsigned long long step0,
