@@ -88,7 +88,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--wg", type=int, default=0, help="workgroups for the disk (0 = library choice)")
     ap.add_argument("--ug", type=int, default=0, help="wavefront groups per workgroup (0 = library choice)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"])
     ap.add_argument("--plain", action="store_true", help="loop over single-disk handles instead of one batch")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
@@ -107,6 +107,8 @@ def main():
     torch.cuda.set_device(0)
     a = 2.0
     PY = li.PERMALLOY
+    if args.workload == "c4":
+        return adjoint_bench(args)
     if args.workload == "c2":
         Rs, Ls = [100.0], [20.0]
         starts = [(10.0, 0.0)]
@@ -232,6 +234,58 @@ def main():
     }
     if not args.no_cpu and args.workload == "c2":
         out["cpu_baseline"] = cpu_baseline(Rs[0], Ls[0], prms[0].dtau, states[0], args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+def adjoint_bench(args):
+    """Adjoint of a 5000-step RK4 trajectory on R=80 nm, L=10 nm (checkpoint every
+    100 steps): time(backward incl. recompute) / time(forward)."""
+    import numpy as np
+    import torch
+
+    import llg_inputs as li
+    from paper_1207_2192_amd import Disk, LLGParams
+    from paper_1207_2192_amd.adjoint import core_trajectory
+    R, L, a = 80.0, 10.0, 2.0
+    disk = Disk.build(R, L, a)
+    D = disk.D[0]
+    n_seg, seg = 50, 100
+    lam = 5.28906
+    m0 = torch.tensor(li.vortex_ansatz(D, 10.0 / a, 0.01), dtype=torch.float32, device="cuda").reshape(-1)
+    base = LLGParams(alpha=0.01, c=C_PY, dtau=0.04)
+    k = torch.arange(n_seg + 1, dtype=torch.float64, device="cuda")
+    target = torch.stack([10.0 * torch.exp(-0.01 * k) * torch.cos(0.2 * k),
+                          10.0 * torch.exp(-0.01 * k) * torch.sin(0.2 * k)], 1)
+    times = []
+    for rep in range(2):
+        m0g = m0.clone().requires_grad_(True)
+        al = torch.tensor(0.01, dtype=torch.float64, requires_grad=True)
+        c = torch.tensor(C_PY, dtype=torch.float64, requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc = core_trajectory(m0g, al, c, disk, base, n_seg, seg, lam)
+        loss = ((rc - target) ** 2).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        disk.check()
+        times.append((t1 - t0, t2 - t1))
+        print(f"# rep {rep}: forward {t1 - t0:.3f} s, backward {t2 - t1:.3f} s, loss {float(loss):.4f}, "
+              f"dL/dalpha {float(al.grad):.4e}, dL/dc {float(c.grad):.4e}", file=sys.stderr, flush=True)
+    fwd, bwd = times[-1]
+    Nc = disk.n_cells[0]
+    steps = n_seg * seg
+    out = {
+        "metric": "adjoint/forward time ratio (RK4 trajectory, checkpointed)",
+        "value": bwd / fwd, "unit": "ratio", "n_gpus": 1, "steps": steps, "warmup": 1,
+        "ms_per_step": fwd / steps * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "adjoint of 5000 RK4 steps, Permalloy R=80 nm L=10 nm a=2 nm (80x80, FFT 256), "
+                               "checkpoint every 100 steps, loss on the core trajectory",
+                   "forward_s": fwd, "backward_s": bwd, "forward_cell_steps_per_s": Nc * steps / fwd},
+    }
     print(json.dumps(out), flush=True)
 
 

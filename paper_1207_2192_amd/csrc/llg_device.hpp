@@ -28,7 +28,7 @@ struct DiskDesc {
     const unsigned char* mask;  // [D][D]
     const float2* tw;         // twiddles [P]
     unsigned int* bar;        // group barrier counter (own cache line)
-    double* part;             // per-workgroup partial sums [G][4]
+    double* part;             // per-workgroup partial sums [G][PART_STRIDE]
 };
 
 // Per-disk parameters (device memory, refreshed when they change).
@@ -38,7 +38,17 @@ struct DiskPrm {
     double c_d, hx_d, hy_d, hz_d;
 };
 
-enum Mode : int { MODE_DEMAG = 0, MODE_RHS = 1, MODE_ENERGY = 2, MODE_RK4 = 3, MODE_HEUN = 4, MODE_RK4_VJP = 5 };
+enum Mode : int {
+    MODE_DEMAG = 0,
+    MODE_RHS = 1,
+    MODE_ENERGY = 2,
+    MODE_RK4 = 3,
+    MODE_HEUN = 4,
+    MODE_RK4_VJP = 5,
+    MODE_RELAX = 6
+};
+
+constexpr int PART_STRIDE = 8;  // doubles of per-workgroup partial sums
 
 enum ErrBits : int { ERR_BARRIER = 1, ERR_NONFINITE = 2 };
 
@@ -55,6 +65,10 @@ struct KArgs {
     unsigned int replica0;
     int mode;
     int* err;
+    // constrained relaxation
+    const double* relax_x;  // target vortex position per disk (2 doubles, units of a from the centre)
+    double* relax_out;      // per disk: lambda_x, lambda_y, sweeps, residual, C_x, C_y, 0, 0
+    double kappa, tol;
 };
 
 // ---------------------------------------------------------------- Philox4x64-10
@@ -126,6 +140,14 @@ __device__ __forceinline__ void st_sh2(float2* p, float2 v) {
         (unsigned long long)__float_as_uint(v.x) | ((unsigned long long)__float_as_uint(v.y) << 32);
     __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ double ld_shd(const double* p) {
+    return __longlong_as_double((long long)__hip_atomic_load(reinterpret_cast<const unsigned long long*>(p),
+                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ void st_shd(double* p, double v) {
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ float4 ld_sh4(const float2* p) {
     const float2 a = ld_sh2(p), b = ld_sh2(p + 1);
     return make_float4(a.x, a.y, b.x, b.y);
@@ -172,6 +194,11 @@ __device__ __forceinline__ bool group_barrier(unsigned int* bar, unsigned int ta
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
     return v;
 }
 

@@ -498,6 +498,87 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         __syncthreads();
     };
 
+
+    // ---- constrained alignment relaxation (one sweep per field evaluation)
+    // cur -> nxt: m <- (b + b^lam + kappa m)/|...| with b^lam = 2 m_z (lam . (r - X)) z-hat.
+    // Thread sums (float64): q[0] = max residual |m x (b + b^lam)| of cur, q[1..2] = C(cur),
+    // q[3..4] = C(nxt), q[5..7] = Jacobian entries (xx, xy, yy) of C(nxt) in lam.
+    double rq[8];
+    auto relax_update = [&](int b, const float* cur, float* nxt, double lx, double ly, double Xc, double Yc) {
+        const double half = (D - 1) / 2.0;
+        const float kap = (float)a.kappa;
+        for (int idx = threadIdx.x; idx < U * D; idx += NT) {
+            const int uu = idx / D, i = idx - uu * D;
+            const int p = b * U + uu;
+            if (p >= d.n_pairs) continue;
+            const int j0 = 2 * p;
+            float col[4][3], lft[2][3], rgt[2][3];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = j0 - 1 + r;
+                const bool ok = j >= 0 && j < D && in_disk(j, i, D);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) col[r][c] = ok ? ld_sh(cur + c * DD + j * D + i) : 0.f;
+            }
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int j = j0 + r;
+                const bool okl = j < D && i > 0 && in_disk(j, i - 1, D);
+                const bool okr = j < D && i + 1 < D && in_disk(j, i + 1, D);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int cell = c * DD + j * D + i;
+                    lft[r][c] = okl ? ld_sh(cur + cell - 1) : 0.f;
+                    rgt[r][c] = okr ? ld_sh(cur + cell + 1) : 0.f;
+                }
+            }
+            const float2 hz2 = BUF(2, uu)[i];
+            float nxt_v[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int j = j0 + r;
+                if (j >= D) break;
+                const int cell = j * D + i;
+                if (in_disk(j, i, D)) {
+                    const float2 hxy = BUF(r, uu)[i];
+                    const float Hz = r == 0 ? hz2.x : hz2.y;
+                    const float mx = col[r + 1][0], my = col[r + 1][1], mz = col[r + 1][2];
+                    const double dx = ((double)i - half) - Xc, dy = ((double)j - half) - Yc;
+                    const float bl = (float)(2.0 * (double)mz * (lx * dx + ly * dy));
+                    const float bx = (col[r][0] + col[r + 2][0] + lft[r][0] + rgt[r][0]) + cf * (hxf + hxy.x);
+                    const float by = (col[r][1] + col[r + 2][1] + lft[r][1] + rgt[r][1]) + cf * (hyf + hxy.y);
+                    const float bz = (col[r][2] + col[r + 2][2] + lft[r][2] + rgt[r][2]) + cf * (hzf + Hz) + bl;
+                    const float px = my * bz - mz * by, py = mz * bx - mx * bz, pz = mx * by - my * bx;
+                    rq[0] = fmax(rq[0], (double)sqrtf(px * px + py * py + pz * pz));
+                    const double w0 = (double)mz * (double)mz;
+                    rq[1] += w0 * dx;
+                    rq[2] += w0 * dy;
+                    const float tx = bx + kap * mx, ty = by + kap * my, tz = bz + kap * mz;
+                    const float tn = sqrtf(tx * tx + ty * ty + tz * tz);
+                    const float inv = tn > 0.f ? 1.0f / tn : 0.f;
+                    const float nx = tx * inv, ny = ty * inv, nz = tz * inv;
+                    const double w1 = (double)nz * (double)nz;
+                    rq[3] += w1 * dx;
+                    rq[4] += w1 * dy;
+                    const double gj = tn > 0.f ? 4.0 * w1 * (1.0 - w1) / (double)tn : 0.0;
+                    rq[5] += gj * dx * dx;
+                    rq[6] += gj * dx * dy;
+                    rq[7] += gj * dy * dy;
+                    nxt_v[r][0] = nx;
+                    nxt_v[r][1] = ny;
+                    nxt_v[r][2] = nz;
+                }
+                st_sh(nxt + cell, nxt_v[r][0]);
+                st_sh(nxt + DD + cell, nxt_v[r][1]);
+                st_sh(nxt + 2 * DD + cell, nxt_v[r][2]);
+            }
+            BUF(0, uu)[i] = make_float2(nxt_v[0][0], nxt_v[0][1]);
+            BUF(1, uu)[i] = make_float2(nxt_v[1][0], nxt_v[1][1]);
+            BUF(2, uu)[i] = make_float2(nxt_v[0][2], nxt_v[1][2]);
+        }
+        __syncthreads();
+    };
+
     auto write_partials = [&](double s0v, double s1v, double s2v) {
         __shared__ double red[3 * MAX_UG][3];
         const double s0 = wave_sum(s0v), s1 = wave_sum(s1v), s2 = wave_sum(s2v);
@@ -511,11 +592,99 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             const int q = threadIdx.x;
             double acc = 0.0;
             for (int w = 0; w < 3 * UG; ++w) acc += red[w][q];
-            d.part[g * 4 + q] = acc;
+            d.part[g * PART_STRIDE + q] = acc;
         }
     };
 
     // ---------------------------------------------------------------- program
+    if (mode == MODE_RELAX) {
+        for (int b = g; b < n_rb; b += G) {
+            load_state_rows(b, m);
+            row_forward_store(b);
+        }
+        if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
+        const double Xc = a.relax_x[2 * d.k], Yc = a.relax_x[2 * d.k + 1];
+        double lx = 0.0, ly = 0.0, res = 0.0, Cx = 0.0, Cy = 0.0;
+        long long sweep = 0;
+        float* cur = m;
+        float* nxt = d.ya;
+        __shared__ double red8[3 * MAX_UG][8];
+        for (; sweep < a.nsteps; ++sweep) {
+            for (int b = g; b < n_cb; b += G) column_phase(b);
+            if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
+            for (int q = 0; q < 8; ++q) rq[q] = 0.0;
+            for (int b = g; b < n_rb; b += G) {
+                row_inverse(b);
+                relax_update(b, cur, nxt, lx, ly, Xc, Yc);
+                row_forward_store(b);
+            }
+            // workgroup partials: max for the residual, sums for the rest
+            {
+                const double v0 = wave_max(rq[0]);
+                double vs[7];
+#pragma unroll
+                for (int q = 1; q < 8; ++q) vs[q - 1] = wave_sum(rq[q]);
+                if (lane == 0) {
+                    red8[wv][0] = v0;
+                    for (int q = 1; q < 8; ++q) red8[wv][q] = vs[q - 1];
+                }
+                __syncthreads();
+                if (threadIdx.x < 8) {
+                    const int q = threadIdx.x;
+                    double acc = 0.0;
+                    for (int w = 0; w < 3 * UG; ++w) acc = (q == 0) ? fmax(acc, red8[w][q]) : acc + red8[w][q];
+                    st_shd(d.part + g * PART_STRIDE + q, acc);
+                }
+            }
+            if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
+            // every workgroup of the disk reduces the same partials in the same order
+            double t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            for (int gg = 0; gg < G; ++gg)
+                for (int q = 0; q < 8; ++q) {
+                    const double v = ld_shd(d.part + gg * PART_STRIDE + q);
+                    t[q] = (q == 0) ? fmax(t[q], v) : t[q] + v;
+                }
+            res = t[0];
+            Cx = t[1];
+            Cy = t[2];
+            if (res < a.tol && fabs(Cx) < a.tol && fabs(Cy) < a.tol) break;   // cur has converged
+            const double jxx = t[5], jxy = t[6], jyy = t[7];
+            const double det = jxx * jyy - jxy * jxy;
+            if (det != 0.0) {
+                lx -= (jyy * t[3] - jxy * t[4]) / det;
+                ly -= (jxx * t[4] - jxy * t[3]) / det;
+            }
+            float* tmp = cur;
+            cur = nxt;
+            nxt = tmp;
+        }
+        // the result lives in cur; bring it back to m
+        if (cur != m) {
+            for (int b = g; b < n_rb; b += G)
+                for (int idx = threadIdx.x; idx < U * D; idx += NT) {
+                    const int uu = idx / D, i = idx - uu * D;
+                    const int p = b * U + uu;
+                    if (p >= d.n_pairs) continue;
+                    for (int r = 0; r < 2; ++r) {
+                        const int j = 2 * p + r;
+                        if (j >= D) break;
+                        for (int c = 0; c < 3; ++c) st_sh(m + c * DD + j * D + i, ld_sh(cur + c * DD + j * D + i));
+                    }
+                }
+        }
+        if (g == 0 && threadIdx.x == 0) {
+            double* o = a.relax_out + 8 * d.k;
+            o[0] = lx;
+            o[1] = ly;
+            o[2] = (double)sweep;
+            o[3] = res;
+            o[4] = Cx;
+            o[5] = Cy;
+            o[6] = 0.0;
+            o[7] = 0.0;
+        }
+        return;
+    }
     if (mode == MODE_RK4_VJP) {
         const long long K = 4 * a.nsteps;
         for (long long k = 0; k <= K; ++k) {
@@ -608,9 +777,9 @@ __global__ void energy_finalize(const DiskDesc* disks, int n, double* out) {
     const DiskDesc d = disks[k];
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for (int g = 0; g < d.G; ++g) {
-        s0 += d.part[g * 4 + 0];
-        s1 += d.part[g * 4 + 1];
-        s2 += d.part[g * 4 + 2];
+        s0 += d.part[g * PART_STRIDE + 0];
+        s1 += d.part[g * PART_STRIDE + 1];
+        s2 += d.part[g * PART_STRIDE + 2];
     }
     out[4 * k + 0] = s0 + s1 + s2;
     out[4 * k + 1] = s0;
@@ -626,8 +795,8 @@ __global__ void grad_finalize(const DiskDesc* disks, int n, double* pgrad) {
     const DiskDesc d = disks[k];
     double s0 = 0.0, s1 = 0.0;
     for (int g = 0; g < d.G; ++g) {
-        s0 += d.part[g * 4 + 0];
-        s1 += d.part[g * 4 + 1];
+        s0 += d.part[g * PART_STRIDE + 0];
+        s1 += d.part[g * PART_STRIDE + 1];
     }
     pgrad[2 * k] += s0;
     pgrad[2 * k + 1] += s1;

@@ -337,7 +337,7 @@ int plan(llg_disk h, int UG, const int* wg_per_disk) {
         DiskDesc& d = h->desc[k];
         h->dfree(d.part);
         d.part = nullptr;
-        if ((rc = h->dalloc(&d.part, (size_t)4 * G[k]))) return rc;
+        if ((rc = h->dalloc(&d.part, (size_t)PART_STRIDE * G[k]))) return rc;
         d.G = G[k];
     }
     h->G = G;
@@ -490,7 +490,8 @@ int upload_params(llg_disk h, const llg_params* p, hipStream_t st) {
 }
 
 int launch(llg_disk h, int mode, float* m, float* out, long long nsteps, unsigned long long seed,
-           unsigned long long step0, unsigned int replica0, hipStream_t st, float* rec = nullptr) {
+           unsigned long long step0, unsigned int replica0, hipStream_t st, float* rec = nullptr,
+           const double* relax_x = nullptr, double* relax_out = nullptr, double kappa = 0.0, double tol = 0.0) {
     const int nb = (h->n_bars + 255) / 256;
     hipLaunchKernelGGL(zero_u32, dim3(nb), dim3(256), 0, st, h->bars, h->n_bars);
     HIP_TRY(hipGetLastError());
@@ -502,6 +503,10 @@ int launch(llg_disk h, int mode, float* m, float* out, long long nsteps, unsigne
     a.m = m;
     a.out = out;
     a.rec = rec;
+    a.relax_x = relax_x;
+    a.relax_out = relax_out;
+    a.kappa = kappa;
+    a.tol = tol;
     a.nsteps = nsteps;
     a.seed = seed;
     a.step0 = step0;
@@ -651,6 +656,22 @@ int llg_core_position_vjp(llg_disk h, const float* m, double lambda_ex_nm, const
                        rbar, h->a_nm, 4.0 * lambda_ex_nm / h->a_nm, mbar);
     HIP_TRY(hipGetLastError());
     return 0;
+}
+
+int llg_relax(llg_disk h, float* m, const double* X_nm, double kappa, double tol, long long max_sweeps,
+              const llg_params* p, double* out, void* stream) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!m || !X_nm || !out) return fail(LLG_EINVAL, "null array");
+    if (!(kappa > 0) || !(tol > 0) || max_sweeps < 1) return fail(LLG_EINVAL, "need kappa > 0, tol > 0, max_sweeps >= 1");
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = upload_params(h, p, st))) return rc;
+    // target positions in units of a from the disk centre, staged like the hints
+    HIP_TRY(hipEventSynchronize(h->hint_event));
+    for (int k = 0; k < 2 * h->n; ++k) h->hint_pin[k] = X_nm[k] / h->a_nm;
+    HIP_TRY(hipMemcpyAsync(h->hint_dev, h->hint_pin, 2 * h->n * sizeof(double), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(h->hint_event, st));
+    return launch(h, MODE_RELAX, m, nullptr, max_sweeps, 0, 0, 0, st, nullptr, h->hint_dev, out, kappa, tol);
 }
 
 int llg_heun_step(llg_disk h, float* m, long long nsteps, unsigned long long seed, unsigned long long step0,
