@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--wg", type=int, default=0, help="workgroups for the disk (0 = library choice)")
     ap.add_argument("--ug", type=int, default=0, help="wavefront groups per workgroup (0 = library choice)")
+    ap.add_argument("--radix", type=int, default=0, help="radix policy for --ug/--wg (0 or 1)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the library's default launch plan")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"])
     ap.add_argument("--plain", action="store_true", help="loop over single-disk handles instead of one batch")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -136,7 +138,7 @@ def main():
                 "Heun T=300 K alpha=0.1 dt=0.02 ps, independent Philox streams")
     disk = Disk.batch(Rs, Ls, a) if len(Rs) > 1 else Disk.build(Rs[0], Ls[0], a)
     if args.wg or args.ug:
-        disk.tune(args.ug or disk.launch_shape()[0], [args.wg] * disk.n if args.wg else None)
+        disk.tune(args.ug or disk.launch_shape()[0], [args.wg] * disk.n if args.wg else None, args.radix)
     Nc = sum(disk.n_cells)
     states = []
     for k in range(disk.n):
@@ -145,6 +147,10 @@ def main():
         states.append(li.vortex_ansatz(disk.D[k], x0 / a + 0.01, y0 / a + 0.013))
     m = torch.tensor(np.concatenate([s.reshape(-1) for s in states]), dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
+    tuned_us = None
+    if not (args.wg or args.ug or args.no_autotune):
+        tuned_us = disk.autotune(m, prms, integrator, probe_steps=300 if disk.n == 1 else 40)
+        print(f"# autotune: {tuned_us:.2f} us/step with plan {disk.launch_shape()}", file=sys.stderr, flush=True)
     step_counter = [0]
 
     plain = None
@@ -227,7 +233,8 @@ def main():
         "config": {"workload": desc, "disks": disk.n, "cells": Nc,
                    "D": sorted(set(disk.D)), "P": sorted(set(disk.P)), "launches": launches,
                    "path": "plain per-disk loop" if plain is not None else "batched persistent launch",
-                   "workgroups": disk.launch_shape()[1], "threads_per_workgroup": disk.launch_shape()[2]},
+                   "workgroups": disk.launch_shape()[1], "threads_per_workgroup": disk.launch_shape()[2],
+                   "radix_policy": disk.launch_shape()[3], "autotuned": tuned_us is not None},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "llg_persistent", "bytes_per_cell_step": b_step / Nc},

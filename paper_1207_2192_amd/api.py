@@ -95,18 +95,30 @@ class Disk:
         check(lib.llg_batch_create(n, R, L, a_nm, W, ctypes.byref(h)), "llg_batch_create")
         return cls(h, dev)
 
-    def tune(self, unit_groups: int, wg_per_disk=None):
-        """Re-plan the persistent launch (llg_tune); results do not depend on it."""
+    def tune(self, unit_groups: int, wg_per_disk=None, radix_policy: int = 0):
+        """Re-plan the persistent launch (llg_tune)."""
         lib = _lib.load()
         W = None if wg_per_disk is None else (ctypes.c_int * self.n)(*[int(w) for w in wg_per_disk])
-        check(lib.llg_tune(self._h, int(unit_groups), W), "llg_tune")
+        check(lib.llg_tune(self._h, int(unit_groups), int(radix_policy), W), "llg_tune")
         self.workgroups = [lib.llg_disk_workgroups(self._h, k) for k in range(self.n)]
 
+    def autotune(self, m: torch.Tensor, params, integrator: str = "rk4", probe_steps: int = 200) -> float:
+        """Time candidate launch plans on a copy of m and keep the fastest (llg_autotune);
+        returns microseconds per step of the chosen plan."""
+        m = self._state(m)
+        best = ctypes.c_double()
+        check(_lib.load().llg_autotune(self._h, _ptr(m), self._params(params), 0 if integrator == "rk4" else 1,
+                                       int(probe_steps), _stream(), ctypes.byref(best)), "llg_autotune")
+        lib = _lib.load()
+        self.workgroups = [lib.llg_disk_workgroups(self._h, k) for k in range(self.n)]
+        return best.value
+
     def launch_shape(self):
-        ug, nwg, nt = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        check(_lib.load().llg_launch_shape(self._h, ctypes.byref(ug), ctypes.byref(nwg), ctypes.byref(nt)),
-              "llg_launch_shape")
-        return ug.value, nwg.value, nt.value
+        """(unit groups, workgroups, threads per workgroup, radix policy)."""
+        ug, nwg, nt, rs = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(_lib.load().llg_launch_shape(self._h, ctypes.byref(ug), ctypes.byref(nwg), ctypes.byref(nt),
+                                           ctypes.byref(rs)), "llg_launch_shape")
+        return ug.value, nwg.value, nt.value, rs.value
 
     def close(self):
         if self._h:

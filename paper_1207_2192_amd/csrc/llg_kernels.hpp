@@ -120,6 +120,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     };
 
     // ---- column kx: forward FFT along y, kernel multiply, inverse FFT along y
+    constexpr int IM = (U * P + NT - 1) / NT;   // spectral points per thread in the multiply
     auto column_phase = [&](int b) {
         const int kx = b * U + u;
         const bool valid = kx < H;
@@ -130,16 +131,30 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             const int i = t + j * Tf;
             v[j] = (valid && i < D) ? ld_sh2(col + i) : make_float2(0.f, 0.f);
         }
-        fft_run<P, R, false>(v, mybuf, ltw, t);
-        for (int idx = threadIdx.x; idx < U * P; idx += NT) {
+        // kernel spectra for this thread's multiply points, loaded with the column
+        float kq4[IM][4];
+#pragma unroll
+        for (int q = 0; q < IM; ++q) {
+            const int idx = threadIdx.x + q * NT;
             const int uu = idx / P, ky = idx - uu * P;
             const int kxx = b * U + uu;
-            if (kxx >= H) continue;
+            const bool ok = idx < U * P && kxx < H;
             const bool lo = ky <= P / 2;
             const int kq = lo ? ky : P - ky;
-            const float* sp = d.spec + (size_t)kxx * H + kq;
-            const float Kxx = sp[0], Kyy = sp[H * H], Kxy = lo ? sp[2 * H * H] : -sp[2 * H * H],
-                        Kzz = sp[3 * H * H];
+            const float* sp = d.spec + (size_t)(ok ? kxx : 0) * H + kq;
+            kq4[q][0] = ok ? sp[0] : 0.f;
+            kq4[q][1] = ok ? sp[H * H] : 0.f;
+            kq4[q][2] = ok ? (lo ? sp[2 * H * H] : -sp[2 * H * H]) : 0.f;
+            kq4[q][3] = ok ? sp[3 * H * H] : 0.f;
+        }
+        fft_run<P, R, false>(v, mybuf, ltw, t);
+#pragma unroll
+        for (int q = 0; q < IM; ++q) {
+            const int idx = threadIdx.x + q * NT;
+            if (idx >= U * P) continue;
+            const int uu = idx / P, ky = idx - uu * P;
+            if (b * U + uu >= H) continue;
+            const float Kxx = kq4[q][0], Kyy = kq4[q][1], Kxy = kq4[q][2], Kzz = kq4[q][3];
             const float2 mx = BUF(0, uu)[ky], my = BUF(1, uu)[ky], mz = BUF(2, uu)[ky];
             BUF(0, uu)[ky] = make_float2(Kxx * mx.x + Kxy * my.x, Kxx * mx.y + Kxy * my.y);
             BUF(1, uu)[ky] = make_float2(Kxy * mx.x + Kyy * my.x, Kxy * mx.y + Kyy * my.y);
@@ -193,36 +208,60 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     // independent loads (one memory latency), then both cells are updated.
     const bool need_y0 = (mode == MODE_RK4) || (mode == MODE_HEUN);
     float* const recd = a.rec ? a.rec + (size_t)a.nsteps * 8 * (size_t)d.m_off : nullptr;
-    auto cell_update = [&](int b, int s, long long n, const float* Ys, float* Yn) {
+    // Gathered values of one column of a row pair (registers).
+    struct Gath {
+        float col[4][3], lft[2][3], rgt[2][3], y0[2][3], ac[2][3];
+    };
+    constexpr int IC = (U * (P / 2) + NT - 1) / NT;   // cell-update items per thread (D <= P/2)
+    Gath gv[IC];
+    auto gather = [&](int b, int s, const float* Ys) {
         const bool need_acc = (mode == MODE_RK4 && s > 0) || (mode == MODE_HEUN && s == 1);
-        for (int idx = threadIdx.x; idx < U * D; idx += NT) {
+#pragma unroll
+        for (int q = 0; q < IC; ++q) {
+            const int idx = threadIdx.x + q * NT;
             const int uu = idx / D, i = idx - uu * D;
             const int p = b * U + uu;
-            if (p >= d.n_pairs) continue;
+            const bool live = idx < U * D && p < d.n_pairs;
             const int j0 = 2 * p;
-            float col[4][3], lft[2][3], rgt[2][3], y0[2][3], ac[2][3];
+            Gath& G_ = gv[q];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int j = j0 - 1 + r;
-                const bool ok = j >= 0 && j < D && in_disk(j, i, D);
+                const bool ok = live && j >= 0 && j < D && in_disk(j, i, D);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) col[r][c] = ok ? ld_sh(Ys + c * DD + j * D + i) : 0.f;
+                for (int c = 0; c < 3; ++c) G_.col[r][c] = ok ? ld_sh(Ys + c * DD + j * D + i) : 0.f;
             }
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
                 const int j = j0 + r;
-                const bool okl = j < D && i > 0 && in_disk(j, i - 1, D);
-                const bool okr = j < D && i + 1 < D && in_disk(j, i + 1, D);
-                const bool okc = j < D && in_disk(j, i, D);
+                const bool okl = live && j < D && i > 0 && in_disk(j, i - 1, D);
+                const bool okr = live && j < D && i + 1 < D && in_disk(j, i + 1, D);
+                const bool okc = live && j < D && in_disk(j, i, D);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const int cell = c * DD + j * D + i;
-                    lft[r][c] = okl ? ld_sh(Ys + cell - 1) : 0.f;
-                    rgt[r][c] = okr ? ld_sh(Ys + cell + 1) : 0.f;
-                    y0[r][c] = (need_y0 && okc) ? ld_sh(m + cell) : 0.f;
-                    ac[r][c] = (need_acc && okc) ? d.acc[cell] : 0.f;
+                    G_.lft[r][c] = okl ? ld_sh(Ys + cell - 1) : 0.f;
+                    G_.rgt[r][c] = okr ? ld_sh(Ys + cell + 1) : 0.f;
+                    G_.y0[r][c] = (need_y0 && okc) ? ld_sh(m + cell) : 0.f;
+                    G_.ac[r][c] = (need_acc && okc) ? d.acc[cell] : 0.f;
                 }
             }
+        }
+    };
+    auto cell_update = [&](int b, int s, long long n, float* Yn) {
+#pragma unroll
+        for (int q = 0; q < IC; ++q) {
+            const int idx = threadIdx.x + q * NT;
+            if (idx >= U * D) continue;
+            const int uu = idx / D, i = idx - uu * D;
+            const int p = b * U + uu;
+            if (p >= d.n_pairs) continue;
+            const int j0 = 2 * p;
+            const float (&col)[4][3] = gv[q].col;
+            const float (&lft)[2][3] = gv[q].lft;
+            const float (&rgt)[2][3] = gv[q].rgt;
+            const float (&y0)[2][3] = gv[q].y0;
+            const float (&ac)[2][3] = gv[q].ac;
             const float2 hz2 = BUF(2, uu)[i];
             float nxt[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
 #pragma unroll
@@ -712,8 +751,9 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         for (int b = g; b < n_cb; b += G) column_phase(b);
         if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
         for (int b = g; b < n_rb; b += G) {
+            gather(b, 0, m);
             row_inverse(b);
-            cell_update(b, 0, 0, m, nullptr);
+            cell_update(b, 0, 0, nullptr);
         }
         if (mode == MODE_ENERGY) write_partials(e_ex, e_dm, e_ext);
         return;
@@ -735,8 +775,9 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                 Yn = (s == 0) ? d.ya : m;
             }
             for (int b = g; b < n_rb; b += G) {
+                gather(b, s, Ys);
                 row_inverse(b);
-                cell_update(b, s, n, Ys, Yn);
+                cell_update(b, s, n, Yn);
                 if (!last) row_forward_store(b);
             }
             if (!last && !group_barrier(d.bar, ++epoch * G, G, a.err)) return;
@@ -745,7 +786,15 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
 #undef BUF
 }
 
-template <int UG>
+// Radix schedule of the LDS transforms: policy 0 uses radix 4 (radix 8 at
+// P = 512, where 64 lanes must carry 512 points); policy 1 uses radix 8 for
+// every size.  The tuner picks the policy per handle.
+template <int P, int RSEL>
+struct Radix {
+    static constexpr int value = (RSEL == 1 || P == 512) ? 8 : 4;
+};
+
+template <int UG, int RSEL>
 __global__ __launch_bounds__(WG_THREADS* UG) void llg_persistent(KArgs a) {
     __shared__ float2 lds[LDS_FFT * UG];
     __shared__ float2 ltw[MAX_P];
@@ -756,10 +805,10 @@ __global__ __launch_bounds__(WG_THREADS* UG) void llg_persistent(KArgs a) {
     const DiskDesc d = a.disks[di];
     const DiskPrm pr = a.prm[di];
     switch (d.P) {
-        case 64: run_disk<64, 4, UG>(a, d, pr, g, lds, ltw); break;
-        case 128: run_disk<128, 4, UG>(a, d, pr, g, lds, ltw); break;
-        case 256: run_disk<256, 4, UG>(a, d, pr, g, lds, ltw); break;
-        case 512: run_disk<512, 8, UG>(a, d, pr, g, lds, ltw); break;
+        case 64: run_disk<64, Radix<64, RSEL>::value, UG>(a, d, pr, g, lds, ltw); break;
+        case 128: run_disk<128, Radix<128, RSEL>::value, UG>(a, d, pr, g, lds, ltw); break;
+        case 256: run_disk<256, Radix<256, RSEL>::value, UG>(a, d, pr, g, lds, ltw); break;
+        case 512: run_disk<512, Radix<512, RSEL>::value, UG>(a, d, pr, g, lds, ltw); break;
         default: break;
     }
 }

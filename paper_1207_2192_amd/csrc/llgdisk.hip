@@ -128,7 +128,7 @@ std::vector<unsigned char> disk_mask(int D, int* n_cells) {
     return m;
 }
 
-int radix_for(int P) { return P == 512 ? 8 : 4; }
+int radix_for(int P, int RSEL) { return (RSEL == 1 || P == 512) ? 8 : 4; }
 
 }  // namespace
 
@@ -160,6 +160,7 @@ struct llg_disk_s {
     int n_bars = 0;
     int* err_dev = nullptr;
     int UG = 1;                       // wavefront groups per workgroup of the persistent launch
+    int RSEL = 0;                     // radix policy of the LDS transforms
     std::vector<DiskDesc> desc;       // host copy of the descriptors
 
     ~llg_disk_s() {
@@ -190,19 +191,26 @@ struct llg_disk_s {
 
 namespace {
 
-const void* persistent_kernel(int UG) {
+const void* persistent_kernel(int UG, int RSEL) {
+    if (RSEL == 1) {
+        switch (UG) {
+            case 1: return reinterpret_cast<const void*>(llg_persistent<1, 1>);
+            case 2: return reinterpret_cast<const void*>(llg_persistent<2, 1>);
+            default: return reinterpret_cast<const void*>(llg_persistent<4, 1>);
+        }
+    }
     switch (UG) {
-        case 1: return reinterpret_cast<const void*>(llg_persistent<1>);
-        case 2: return reinterpret_cast<const void*>(llg_persistent<2>);
-        default: return reinterpret_cast<const void*>(llg_persistent<4>);
+        case 1: return reinterpret_cast<const void*>(llg_persistent<1, 0>);
+        case 2: return reinterpret_cast<const void*>(llg_persistent<2, 0>);
+        default: return reinterpret_cast<const void*>(llg_persistent<4, 0>);
     }
 }
 
-int max_coresident_workgroups(int UG, int* out) {
+int max_coresident_workgroups(int UG, int RSEL, int* out) {
     int dev = 0, ncu = 0, per_cu = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel(UG), WG_THREADS * UG, 0));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel(UG, RSEL), WG_THREADS * UG, 0));
     *out = ncu * per_cu;
     return 0;
 }
@@ -223,27 +231,27 @@ int choose_P(int D, int P_override, int* P) {
 }
 
 // Units (transforms per component) a workgroup carries at once, for FFT size P.
-int units_per_wg(int P, int UG) { return UG * (64 / (P / radix_for(P))); }
+int units_per_wg(int P, int UG, int RSEL) { return UG * (64 / (P / radix_for(P, RSEL))); }
 
-int default_unit_groups(llg_disk h) {
-    // a lone disk wants few, wide workgroups (each group barrier costs about
-    // 0.35 us per workgroup per XCD); a batch of many disks wants one narrow
-    // workgroup group per small disk
-    return h->n == 1 ? 4 : 1;
+int default_unit_groups(llg_disk) {
+    // narrow workgroups spread a disk over the most CUs; measured best for a
+    // lone D=100 disk (one transform per workgroup and phase) and for batches
+    return 1;
 }
 
 // Workgroups per disk and the workgroup-to-disk map of the persistent launch.
-int plan(llg_disk h, int UG, const int* wg_per_disk) {
+int plan(llg_disk h, int UG, int RSEL, const int* wg_per_disk) {
     if (UG != 1 && UG != 2 && UG != 4) return fail(LLG_EINVAL, "unit groups must be 1, 2 or 4");
+    if (RSEL != 0 && RSEL != 1) return fail(LLG_EINVAL, "radix policy must be 0 or 1");
     const int n = h->n;
     int cap = 0;
-    int rc = max_coresident_workgroups(UG, &cap);
+    int rc = max_coresident_workgroups(UG, RSEL, &cap);
     if (rc) return rc;
     std::vector<int> useful(n), G(n);
     std::vector<double> work(n);
     for (int k = 0; k < n; ++k) {
         const int P = h->P[k], D = h->D[k];
-        const int U = units_per_wg(P, UG);
+        const int U = units_per_wg(P, UG, RSEL);
         const int H = P / 2 + 1;
         const int n_pairs = (D + 1) / 2;
         useful[k] = std::max((n_pairs + U - 1) / U, (H + U - 1) / U);
@@ -342,6 +350,7 @@ int plan(llg_disk h, int UG, const int* wg_per_disk) {
     }
     h->G = G;
     h->UG = UG;
+    h->RSEL = RSEL;
     if (!h->desc_dev && (rc = h->dalloc(&h->desc_dev, n))) return rc;
     HIP_TRY(hipMemcpy(h->desc_dev, h->desc.data(), n * sizeof(DiskDesc), hipMemcpyHostToDevice));
     return 0;
@@ -441,7 +450,7 @@ int create(int n, const double* R_nm, const double* L_nm, double a_nm, const int
         d.tw = h->twiddles[d.P];
         d.bar = h->bars + 32 * k;
     }
-    if ((rc = plan(h, default_unit_groups(h), wg_per_disk))) return bail(rc);
+    if ((rc = plan(h, default_unit_groups(h), 0, wg_per_disk))) return bail(rc);
     if ((rc = h->dalloc(&h->prm_dev, n))) return bail(rc);
     if ((rc = h->dalloc(&h->hint_dev, 2 * (size_t)n))) return bail(rc);
     HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->prm_pin), n * sizeof(DiskPrm), hipHostMallocDefault));
@@ -514,7 +523,7 @@ int launch(llg_disk h, int mode, float* m, float* out, long long nsteps, unsigne
     a.mode = mode;
     a.err = h->err_dev;
     void* args[] = {&a};
-    HIP_TRY(hipLaunchCooperativeKernel(persistent_kernel(h->UG), dim3(h->n_wg), dim3(WG_THREADS * h->UG), args, 0,
+    HIP_TRY(hipLaunchCooperativeKernel(persistent_kernel(h->UG, h->RSEL), dim3(h->n_wg), dim3(WG_THREADS * h->UG), args, 0,
                                        st));
     return 0;
 }
@@ -581,18 +590,81 @@ int llg_disk_workgroups(llg_disk h, int k) {
     return h->G[k];
 }
 
-int llg_tune(llg_disk h, int unit_groups, const int* wg_per_disk) {
+int llg_tune(llg_disk h, int unit_groups, int radix_policy, const int* wg_per_disk) {
     int rc = check_handle(h);
     if (rc) return rc;
     HIP_TRY(hipDeviceSynchronize());
-    return plan(h, unit_groups, wg_per_disk);
+    return plan(h, unit_groups, radix_policy, wg_per_disk);
 }
 
-int llg_launch_shape(llg_disk h, int* unit_groups, int* workgroups, int* threads) {
+int llg_launch_shape(llg_disk h, int* unit_groups, int* workgroups, int* threads, int* radix_policy) {
     if (!h) return fail(LLG_EINVAL, "null handle");
+    if (radix_policy) *radix_policy = h->RSEL;
     if (unit_groups) *unit_groups = h->UG;
     if (workgroups) *workgroups = h->n_wg;
     if (threads) *threads = WG_THREADS * h->UG;
+    return 0;
+}
+
+int llg_autotune(llg_disk h, const float* m, const llg_params* p, int integrator, long long probe_steps,
+                 void* stream, double* best_us) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!m || !p) return fail(LLG_EINVAL, "null array");
+    if (integrator != 0 && integrator != 1) return fail(LLG_EINVAL, "integrator: 0 = RK4, 1 = Heun");
+    if (probe_steps < 1) return fail(LLG_EINVAL, "probe_steps < 1");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipStreamSynchronize(st));
+    float* work = nullptr;
+    HIP_TRY(hipMalloc(&work, h->state_size * sizeof(float)));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int mode = integrator == 0 ? MODE_RK4 : MODE_HEUN;
+    llg_params* pp = const_cast<llg_params*>(p);
+    if ((rc = upload_params(h, pp, st))) return rc;
+    // candidate plans: unit groups x radix policy x workgroup scale
+    std::vector<int> base(h->n);
+    struct Cand { int UG, RSEL; double scale; };
+    std::vector<Cand> cands;
+    for (int ug : {1, 2, 4})
+        for (int rs : {0, 1})
+            for (double sc : {1.0, 0.5, 0.25}) cands.push_back({ug, rs, sc});
+    double best = 1e300;
+    Cand bestc{h->UG, h->RSEL, 1.0};
+    std::vector<int> bestG = h->G;
+    for (const Cand& c : cands) {
+        if ((rc = plan(h, c.UG, c.RSEL, nullptr))) continue;
+        std::vector<int> G = h->G;
+        for (int k = 0; k < h->n; ++k) G[k] = std::max(1, (int)std::lround(G[k] * c.scale));
+        if ((rc = plan(h, c.UG, c.RSEL, G.data()))) continue;
+        float ms = 0.f;
+        bool ok = true;
+        for (int rep = 0; rep < 2 && ok; ++rep) {
+            HIP_TRY(hipMemcpyAsync(work, m, h->state_size * sizeof(float), hipMemcpyDeviceToDevice, st));
+            HIP_TRY(hipEventRecord(e0, st));
+            if (launch(h, mode, work, nullptr, probe_steps, 1, 0, 0, st)) ok = false;
+            HIP_TRY(hipEventRecord(e1, st));
+            HIP_TRY(hipEventSynchronize(e1));
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        }
+        int e = 0;
+        HIP_TRY(hipMemcpy(&e, h->err_dev, sizeof(int), hipMemcpyDeviceToHost));
+        if (e) {
+            HIP_TRY(hipMemset(h->err_dev, 0, sizeof(int)));
+            ok = false;
+        }
+        if (ok && ms > 0 && ms < best) {
+            best = ms;
+            bestc = c;
+            bestG = h->G;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(work);
+    if ((rc = plan(h, bestc.UG, bestc.RSEL, bestG.data()))) return rc;
+    if (best_us) *best_us = best * 1e3 / (double)probe_steps;
     return 0;
 }
 

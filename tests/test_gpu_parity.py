@@ -270,10 +270,43 @@ def test_launch_plan_does_not_change_results():
     p = Prm(alpha=0.05, c=C_PY, dtau=0.04)
     outs = []
     for ug, wg in ((1, None), (1, [7]), (2, [5]), (4, [3]), (4, None), (2, [1])):
-        disk.tune(ug, wg)
+        disk.tune(ug, wg, 0)
         m = m0.clone()
         disk.rk4_step(m, 6, p)
         disk.check()
         outs.append(m)
     for o in outs[1:]:
         assert torch.equal(o, outs[0])
+
+
+@pytest.mark.parametrize("R,L,P", [(15.0, 5.0, 0), (30.0, 10.0, 0), (61.0, 12.0, 0), (100.0, 20.0, 0),
+                                   (120.0, 10.0, 512)])
+@pytest.mark.parametrize("ug", [1, 4])
+def test_radix8_policy_matches_oracle(R, L, P, ug):
+    Disk, Prm = gpu()
+    disk = Disk.build(R, L, 2.0, P)
+    disk.tune(ug, None, 1)
+    od = oracle.Disk(R, L, 2.0, P=P or None)
+    D = disk.D[0]
+    m0 = state_in(D, 21 + D)
+    H = disk.demag_field(to_dev(m0)).view(3, D, D).double().cpu()
+    assert rel(H, demag_fft(torch.tensor(m0), od)) <= 1e-5
+    p = Prm(alpha=0.1, c=C_PY)
+    f = disk.rhs(to_dev(m0), p).view(3, D, D).double().cpu()
+    assert rel(f, o_rhs(torch.tensor(m0), od, oracle.Params(alpha=0.1, c=C_PY))) <= 1e-5
+
+
+def test_autotune_keeps_parity():
+    Disk, Prm = gpu()
+    disk = Disk.build(61.0, 12.0)
+    od = oracle.Disk(61.0, 12.0)
+    D = disk.D[0]
+    m0 = state_in(D, 5, "vortex")
+    p = Prm(alpha=0.02, c=C_PY, dtau=0.04)
+    us = disk.autotune(to_dev(m0), p, "rk4", probe_steps=20)
+    assert us > 0
+    m = to_dev(m0)
+    disk.rk4_step(m, 5, p)
+    disk.check()
+    ref = o_rk4(torch.tensor(m0), od, oracle.Params(alpha=0.02, c=C_PY, dtau=0.04), 5)
+    assert float((m.view(3, D, D).double().cpu() - ref).abs().max()) <= 5e-6
