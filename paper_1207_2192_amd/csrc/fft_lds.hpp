@@ -82,9 +82,16 @@ __device__ __forceinline__ void dftR(float2* x) {
 
 constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 
+// LDS layout of a transform buffer: one padding slot after every 16 complex
+// values, so that the strided Stockham writes of a 16-lane group land in 16
+// different bank pairs.
+__device__ __forceinline__ int pad16(int e) { return e + (e >> 4); }
+template <int P>
+constexpr int padded_len() { return P + P / 16; }
+
 // One length-P transform by the lanes t = 0 .. P/R-1 of a lane group.
-// On entry v[j] = x[t + j*(P/R)].  On exit buf[0..P) holds X in natural
-// order.  buf may alias the input storage; tw is the P-entry twiddle table.
+// On entry v[j] = x[t + j*(P/R)].  On exit buf holds X in natural order
+// (element e at buf[pad16(e)]).  buf may alias the input storage; tw is the P-entry twiddle table.
 // Every lane of the workgroup must call this the same number of times
 // (it contains workgroup barriers).
 template <int P, int R, bool INV>
@@ -99,7 +106,7 @@ __device__ __forceinline__ void fft_run(float2 (&v)[R], float2* buf, const float
     for (int s = 0; s < NFULL; ++s) {
         if (s > 0) {
 #pragma unroll
-            for (int j = 0; j < R; ++j) v[j] = buf[t + j * Tf];
+            for (int j = 0; j < R; ++j) v[j] = buf[pad16(t + j * Tf)];
             const int kk = t & (Ns - 1);
             const int stp = kk * (P / (Ns * R));
 #pragma unroll
@@ -113,7 +120,7 @@ __device__ __forceinline__ void fft_run(float2 (&v)[R], float2* buf, const float
         const int base = (t - kk) * R + kk;
         __syncthreads();
 #pragma unroll
-        for (int j = 0; j < R; ++j) buf[base + j * Ns] = v[j];
+        for (int j = 0; j < R; ++j) buf[pad16(base + j * Ns)] = v[j];
         __syncthreads();
         Ns *= R;
     }
@@ -127,7 +134,7 @@ __device__ __forceinline__ void fft_run(float2 (&v)[R], float2* buf, const float
             const int stp = kk * (P / (Ns * REM));
 #pragma unroll
             for (int j = 0; j < REM; ++j) {
-                float2 x = buf[k + j * (P / REM)];
+                float2 x = buf[pad16(k + j * (P / REM))];
                 if (j > 0) {
                     const float2 w = tw[(j * stp) & (P - 1)];
                     x = INV ? cmulc(x, w) : cmul(x, w);
@@ -143,7 +150,7 @@ __device__ __forceinline__ void fft_run(float2 (&v)[R], float2* buf, const float
             const int kk = k & (Ns - 1);
             const int base = (k - kk) * REM + kk;
 #pragma unroll
-            for (int j = 0; j < REM; ++j) buf[base + j * Ns] = u[q * REM + j];
+            for (int j = 0; j < REM; ++j) buf[pad16(base + j * Ns)] = u[q * REM + j];
         }
         __syncthreads();
     }

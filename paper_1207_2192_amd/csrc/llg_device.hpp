@@ -12,7 +12,7 @@ constexpr int WG_THREADS = 192;   // one group of three wavefronts: components x
 constexpr int MAX_UG = 4;         // wavefront groups per workgroup
 constexpr int MAX_P = 512;
 constexpr int MAX_R = 8;
-constexpr int LDS_FFT = 3 * 64 * MAX_R;   // float2 slots per group: 3 waves x (64/Tf units) x P = 3*64*R
+constexpr int LDS_FFT = 3 * 64 * MAX_R * 17 / 16;   // float2 per group: 3 waves x (64/Tf units) x padded P
 
 // Per-disk descriptor (device memory, written once by the host).
 struct DiskDesc {

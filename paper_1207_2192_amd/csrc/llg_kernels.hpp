@@ -31,7 +31,7 @@ __device__ __forceinline__ bool in_disk(int j, int i, int D) {
     return x * x + y * y <= D * D;
 }
 
-template <int P, int R, int UG>
+template <int P, int R, int UG, int MODE>
 __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, const DiskPrm& pr, int g,
                                          float2* lds, float2* ltw) {
     constexpr int Tf = P / R;
@@ -43,8 +43,9 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wave = wv % 3, grp = wv / 3;     // wave = component (or packed row) of the group
     const int u = grp * (64 / Tf) + lane / Tf, t = lane % Tf;
-    float2* const mybuf = lds + (wave * U + u) * P;
-#define BUF(w, uu) (lds + ((w) * U + (uu)) * P)
+    constexpr int PS = padded_len<P>();
+    float2* const mybuf = lds + (wave * U + u) * PS;
+#define BUF(w, uu) (lds + ((w) * U + (uu)) * PS)
 
     for (int i = threadIdx.x; i < P; i += NT) ltw[i] = d.tw[i];
     __syncthreads();
@@ -56,7 +57,8 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     const int n_rb = (d.n_pairs + U - 1) / U;
     const int n_cb = (H + U - 1) / U;
     unsigned int epoch = 0;
-    const int mode = a.mode;
+    // the field kernel serves demag / rhs / energy at run time; the integrators are compiled per mode
+    const int mode = (MODE == MODE_DEMAG) ? a.mode : MODE;
 
     // ---- packed rows of a state into LDS (masked), columns [0, D)
     auto load_state_rows = [&](int b, const float* src) {
@@ -80,9 +82,9 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                     }
                 }
             }
-            BUF(0, uu)[i] = make_float2(x0, y0);
-            BUF(1, uu)[i] = make_float2(x1, y1);
-            BUF(2, uu)[i] = make_float2(z0, z1);
+            BUF(0, uu)[pad16(i)] = make_float2(x0, y0);
+            BUF(1, uu)[pad16(i)] = make_float2(x1, y1);
+            BUF(2, uu)[pad16(i)] = make_float2(z0, z1);
         }
         __syncthreads();
     };
@@ -93,7 +95,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const int i = t + j * Tf;
-            v[j] = (i < D) ? mybuf[i] : make_float2(0.f, 0.f);
+            v[j] = (i < D) ? mybuf[pad16(i)] : make_float2(0.f, 0.f);
         }
         fft_run<P, R, false>(v, mybuf, ltw, t);
         for (int idx = threadIdx.x; idx < U * H; idx += NT) {
@@ -102,9 +104,9 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             if (p >= d.n_pairs) continue;
             const int j0 = 2 * p;
             const int km = (P - k) & (P - 1);
-            const float2 A0 = BUF(0, uu)[k], B0 = BUF(0, uu)[km];
-            const float2 A1 = BUF(1, uu)[k], B1 = BUF(1, uu)[km];
-            const float2 A2 = BUF(2, uu)[k], B2 = BUF(2, uu)[km];
+            const float2 A0 = BUF(0, uu)[pad16(k)], B0 = BUF(0, uu)[pad16(km)];
+            const float2 A1 = BUF(1, uu)[pad16(k)], B1 = BUF(1, uu)[pad16(km)];
+            const float2 A2 = BUF(2, uu)[pad16(k)], B2 = BUF(2, uu)[pad16(km)];
             // two real rows packed as a + i b:  a^ = (A + conj B)/2,  b^ = (A - conj B)/(2i)
             const float4 sx = make_float4(0.5f * (A0.x + B0.x), 0.5f * (A0.y - B0.y),
                                           0.5f * (A1.x + B1.x), 0.5f * (A1.y - B1.y));
@@ -155,17 +157,17 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             const int uu = idx / P, ky = idx - uu * P;
             if (b * U + uu >= H) continue;
             const float Kxx = kq4[q][0], Kyy = kq4[q][1], Kxy = kq4[q][2], Kzz = kq4[q][3];
-            const float2 mx = BUF(0, uu)[ky], my = BUF(1, uu)[ky], mz = BUF(2, uu)[ky];
-            BUF(0, uu)[ky] = make_float2(Kxx * mx.x + Kxy * my.x, Kxx * mx.y + Kxy * my.y);
-            BUF(1, uu)[ky] = make_float2(Kxy * mx.x + Kyy * my.x, Kxy * mx.y + Kyy * my.y);
-            BUF(2, uu)[ky] = make_float2(Kzz * mz.x, Kzz * mz.y);
+            const float2 mx = BUF(0, uu)[pad16(ky)], my = BUF(1, uu)[pad16(ky)], mz = BUF(2, uu)[pad16(ky)];
+            BUF(0, uu)[pad16(ky)] = make_float2(Kxx * mx.x + Kxy * my.x, Kxx * mx.y + Kxy * my.y);
+            BUF(1, uu)[pad16(ky)] = make_float2(Kxy * mx.x + Kyy * my.x, Kxy * mx.y + Kyy * my.y);
+            BUF(2, uu)[pad16(ky)] = make_float2(Kzz * mz.x, Kzz * mz.y);
         }
         __syncthreads();
 #pragma unroll
-        for (int j = 0; j < R; ++j) v[j] = mybuf[t + j * Tf];
+        for (int j = 0; j < R; ++j) v[j] = mybuf[pad16(t + j * Tf)];
         fft_run<P, R, true>(v, mybuf, ltw, t);
         if (valid)
-            for (int i = t; i < D; i += Tf) st_sh2(col + i, mybuf[i]);
+            for (int i = t; i < D; i += Tf) st_sh2(col + i, mybuf[pad16(i)]);
         __syncthreads();
     };
 
@@ -182,20 +184,20 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                 sz = ld_sh4(S + (size_t)(2 * H + k) * Dp + j0);
             }
             // Hx + i Hy of each row, Hz(j0) + i Hz(j1); mirrored half from Hermitian symmetry
-            BUF(0, uu)[k] = make_float2(sx.x - sy.y, sx.y + sy.x);
-            BUF(1, uu)[k] = make_float2(sx.z - sy.w, sx.w + sy.z);
-            BUF(2, uu)[k] = make_float2(sz.x - sz.w, sz.y + sz.z);
+            BUF(0, uu)[pad16(k)] = make_float2(sx.x - sy.y, sx.y + sy.x);
+            BUF(1, uu)[pad16(k)] = make_float2(sx.z - sy.w, sx.w + sy.z);
+            BUF(2, uu)[pad16(k)] = make_float2(sz.x - sz.w, sz.y + sz.z);
             if (k > 0 && k < P / 2) {
                 const int km = P - k;
-                BUF(0, uu)[km] = make_float2(sx.x + sy.y, sy.x - sx.y);
-                BUF(1, uu)[km] = make_float2(sx.z + sy.w, sy.z - sx.w);
-                BUF(2, uu)[km] = make_float2(sz.x + sz.w, sz.z - sz.y);
+                BUF(0, uu)[pad16(km)] = make_float2(sx.x + sy.y, sy.x - sx.y);
+                BUF(1, uu)[pad16(km)] = make_float2(sx.z + sy.w, sy.z - sx.w);
+                BUF(2, uu)[pad16(km)] = make_float2(sz.x + sz.w, sz.z - sz.y);
             }
         }
         __syncthreads();
         float2 v[R];
 #pragma unroll
-        for (int j = 0; j < R; ++j) v[j] = mybuf[t + j * Tf];
+        for (int j = 0; j < R; ++j) v[j] = mybuf[pad16(t + j * Tf)];
         fft_run<P, R, true>(v, mybuf, ltw, t);
     };
 
@@ -262,7 +264,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             const float (&rgt)[2][3] = gv[q].rgt;
             const float (&y0)[2][3] = gv[q].y0;
             const float (&ac)[2][3] = gv[q].ac;
-            const float2 hz2 = BUF(2, uu)[i];
+            const float2 hz2 = BUF(2, uu)[pad16(i)];
             float nxt[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
@@ -270,7 +272,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                 if (j >= D) break;
                 const int cell = j * D + i;
                 const bool in = in_disk(j, i, D);
-                const float2 hxy = BUF(r, uu)[i];
+                const float2 hxy = BUF(r, uu)[pad16(i)];
                 const float Hx = hxy.x, Hy = hxy.y, Hz = r == 0 ? hz2.x : hz2.y;
                 if (mode == MODE_DEMAG) {
                     out[cell] = in ? Hx : 0.f;
@@ -382,9 +384,9 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                 nxt[r][2] = nzv;
             }
             if (mode == MODE_RK4 || mode == MODE_HEUN) {
-                BUF(0, uu)[i] = make_float2(nxt[0][0], nxt[0][1]);
-                BUF(1, uu)[i] = make_float2(nxt[1][0], nxt[1][1]);
-                BUF(2, uu)[i] = make_float2(nxt[0][2], nxt[1][2]);
+                BUF(0, uu)[pad16(i)] = make_float2(nxt[0][0], nxt[0][1]);
+                BUF(1, uu)[pad16(i)] = make_float2(nxt[1][0], nxt[1][1]);
+                BUF(2, uu)[pad16(i)] = make_float2(nxt[0][2], nxt[1][2]);
             }
         }
         __syncthreads();
@@ -447,7 +449,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                     yb0[r][c] = (sta && okc) ? ld_sh(m + cell) : 0.f;
                 }
             }
-            const float2 hz2 = BUF(2, uu)[i];
+            const float2 hz2 = BUF(2, uu)[pad16(i)];
             float nxt[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
@@ -465,7 +467,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                 float yprev[3] = {0.f, 0.f, 0.f};
                 float ybar[3] = {yb0[r][0], yb0[r][1], yb0[r][2]};
                 if (fin) {
-                    const float2 kxy = BUF(r, uu)[i];
+                    const float2 kxy = BUF(r, uu)[pad16(i)];
                     const float Kb[3] = {kxy.x, kxy.y, r == 0 ? hz2.x : hz2.y};
                     float accn[3];
 #pragma unroll
@@ -529,9 +531,9 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                 }
             }
             if (sta) {
-                BUF(0, uu)[i] = make_float2(nxt[0][0], nxt[0][1]);
-                BUF(1, uu)[i] = make_float2(nxt[1][0], nxt[1][1]);
-                BUF(2, uu)[i] = make_float2(nxt[0][2], nxt[1][2]);
+                BUF(0, uu)[pad16(i)] = make_float2(nxt[0][0], nxt[0][1]);
+                BUF(1, uu)[pad16(i)] = make_float2(nxt[1][0], nxt[1][1]);
+                BUF(2, uu)[pad16(i)] = make_float2(nxt[0][2], nxt[1][2]);
             }
         }
         __syncthreads();
@@ -571,7 +573,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                     rgt[r][c] = okr ? ld_sh(cur + cell + 1) : 0.f;
                 }
             }
-            const float2 hz2 = BUF(2, uu)[i];
+            const float2 hz2 = BUF(2, uu)[pad16(i)];
             float nxt_v[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
@@ -579,7 +581,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                 if (j >= D) break;
                 const int cell = j * D + i;
                 if (in_disk(j, i, D)) {
-                    const float2 hxy = BUF(r, uu)[i];
+                    const float2 hxy = BUF(r, uu)[pad16(i)];
                     const float Hz = r == 0 ? hz2.x : hz2.y;
                     const float mx = col[r + 1][0], my = col[r + 1][1], mz = col[r + 1][2];
                     const double dx = ((double)i - half) - Xc, dy = ((double)j - half) - Yc;
@@ -611,9 +613,9 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                 st_sh(nxt + DD + cell, nxt_v[r][1]);
                 st_sh(nxt + 2 * DD + cell, nxt_v[r][2]);
             }
-            BUF(0, uu)[i] = make_float2(nxt_v[0][0], nxt_v[0][1]);
-            BUF(1, uu)[i] = make_float2(nxt_v[1][0], nxt_v[1][1]);
-            BUF(2, uu)[i] = make_float2(nxt_v[0][2], nxt_v[1][2]);
+            BUF(0, uu)[pad16(i)] = make_float2(nxt_v[0][0], nxt_v[0][1]);
+            BUF(1, uu)[pad16(i)] = make_float2(nxt_v[1][0], nxt_v[1][1]);
+            BUF(2, uu)[pad16(i)] = make_float2(nxt_v[0][2], nxt_v[1][2]);
         }
         __syncthreads();
     };
@@ -636,7 +638,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     };
 
     // ---------------------------------------------------------------- program
-    if (mode == MODE_RELAX) {
+    if constexpr (MODE == MODE_RELAX) {
         for (int b = g; b < n_rb; b += G) {
             load_state_rows(b, m);
             row_forward_store(b);
@@ -724,7 +726,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         }
         return;
     }
-    if (mode == MODE_RK4_VJP) {
+    else if constexpr (MODE == MODE_RK4_VJP) {
         const long long K = 4 * a.nsteps;
         for (long long k = 0; k <= K; ++k) {
             for (int b = g; b < n_rb; b += G) {
@@ -741,13 +743,14 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         return;
     }
 
+    else {
     for (int b = g; b < n_rb; b += G) {
         load_state_rows(b, m);
         row_forward_store(b);
     }
     if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
 
-    if (mode == MODE_DEMAG || mode == MODE_RHS || mode == MODE_ENERGY) {
+    if constexpr (MODE == MODE_DEMAG) {
         for (int b = g; b < n_cb; b += G) column_phase(b);
         if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
         for (int b = g; b < n_rb; b += G) {
@@ -759,7 +762,8 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         return;
     }
 
-    const int nst = (mode == MODE_RK4) ? 4 : 2;
+    else {
+    constexpr int nst = (MODE == MODE_RK4) ? 4 : 2;
     for (long long n = 0; n < a.nsteps; ++n) {
         for (int s = 0; s < nst; ++s) {
             for (int b = g; b < n_cb; b += G) column_phase(b);
@@ -783,6 +787,8 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             if (!last && !group_barrier(d.bar, ++epoch * G, G, a.err)) return;
         }
     }
+    }
+    }
 #undef BUF
 }
 
@@ -794,7 +800,11 @@ struct Radix {
     static constexpr int value = (RSEL == 1 || P == 512) ? 8 : 4;
 };
 
-template <int UG, int RSEL>
+// One persistent kernel per (workgroup shape UG, radix policy RSEL, mode,
+// largest FFT size PMAX of the handle): each instance carries only the code
+// and registers of its own path.  MODE_DEMAG stands for the field kernel
+// (demag, rhs and energy, chosen at run time).
+template <int UG, int RSEL, int MODE, int PMAX>
 __global__ __launch_bounds__(WG_THREADS* UG) void llg_persistent(KArgs a) {
     __shared__ float2 lds[LDS_FFT * UG];
     __shared__ float2 ltw[MAX_P];
@@ -805,261 +815,28 @@ __global__ __launch_bounds__(WG_THREADS* UG) void llg_persistent(KArgs a) {
     const DiskDesc d = a.disks[di];
     const DiskPrm pr = a.prm[di];
     switch (d.P) {
-        case 64: run_disk<64, Radix<64, RSEL>::value, UG>(a, d, pr, g, lds, ltw); break;
-        case 128: run_disk<128, Radix<128, RSEL>::value, UG>(a, d, pr, g, lds, ltw); break;
-        case 256: run_disk<256, Radix<256, RSEL>::value, UG>(a, d, pr, g, lds, ltw); break;
-        case 512: run_disk<512, Radix<512, RSEL>::value, UG>(a, d, pr, g, lds, ltw); break;
+        case 64: run_disk<64, Radix<64, RSEL>::value, UG, MODE>(a, d, pr, g, lds, ltw); break;
+        case 128: run_disk<128, Radix<128, RSEL>::value, UG, MODE>(a, d, pr, g, lds, ltw); break;
+        case 256: run_disk<256, Radix<256, RSEL>::value, UG, MODE>(a, d, pr, g, lds, ltw); break;
+        case 512:
+            if constexpr (PMAX >= 512) run_disk<512, Radix<512, RSEL>::value, UG, MODE>(a, d, pr, g, lds, ltw);
+            break;
         default: break;
     }
 }
 
-__global__ void zero_u32(unsigned int* p, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0u;
-}
-
-// E = E_ex + E_demag + E_ext per disk from the per-workgroup partials, summed in
-// workgroup order (deterministic).
-__global__ void energy_finalize(const DiskDesc* disks, int n, double* out) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    const DiskDesc d = disks[k];
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int g = 0; g < d.G; ++g) {
-        s0 += d.part[g * PART_STRIDE + 0];
-        s1 += d.part[g * PART_STRIDE + 1];
-        s2 += d.part[g * PART_STRIDE + 2];
-    }
-    out[4 * k + 0] = s0 + s1 + s2;
-    out[4 * k + 1] = s0;
-    out[4 * k + 2] = s1;
-    out[4 * k + 3] = s2;
-}
-
-// Adjoint parameter gradients: pgrad[2k] += alpha_bar, pgrad[2k+1] += c_bar of disk k,
-// summed over the per-workgroup partials in workgroup order.
-__global__ void grad_finalize(const DiskDesc* disks, int n, double* pgrad) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    const DiskDesc d = disks[k];
-    double s0 = 0.0, s1 = 0.0;
-    for (int g = 0; g < d.G; ++g) {
-        s0 += d.part[g * PART_STRIDE + 0];
-        s1 += d.part[g * PART_STRIDE + 1];
-    }
-    pgrad[2 * k] += s0;
-    pgrad[2 * k + 1] += s1;
-}
-
-// Noise field of one Heun step (test hook), packed like the state.
-__global__ void noise_kernel(const DiskDesc* disks, int n, float* w, unsigned long long seed,
-                             unsigned long long step, unsigned int replica0) {
-    const int k = blockIdx.y;
-    if (k >= n) return;
-    const DiskDesc d = disks[k];
-    const int DD = d.D * d.D;
-    float* out = w + d.m_off;
-    for (int cell = blockIdx.x * blockDim.x + threadIdx.x; cell < DD; cell += gridDim.x * blockDim.x) {
-        float3 v = make_float3(0.f, 0.f, 0.f);
-        if (d.mask[cell]) v = thermal_normals(seed, step, (unsigned long long)cell, (unsigned long long)(replica0 + d.k));
-        out[cell] = v.x;
-        out[DD + cell] = v.y;
-        out[2 * DD + cell] = v.z;
-    }
-}
-
-constexpr int OBS_THREADS = 256;
-
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-    v = wave_sum(v);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    __syncthreads();
-    if (lane == 0) sh[wave] = v;
-    __syncthreads();
-    double s = 0.0;
-    for (int w = 0; w < OBS_THREADS / 64; ++w) s += sh[w];
-    return s;
-}
-
-// <m> per disk, float64.
-__global__ __launch_bounds__(OBS_THREADS) void mean_kernel(const DiskDesc* disks, const float* m_base, double* out) {
-    __shared__ double sh[OBS_THREADS / 64];
-    const DiskDesc d = disks[blockIdx.x];
-    const int DD = d.D * d.D;
-    const float* m = m_base + d.m_off;
-    double sx = 0.0, sy = 0.0, sz = 0.0;
-    for (int c = threadIdx.x; c < DD; c += OBS_THREADS)
-        if (d.mask[c]) {
-            sx += m[c];
-            sy += m[DD + c];
-            sz += m[2 * DD + c];
-        }
-    sx = block_sum(sx, sh);
-    sy = block_sum(sy, sh);
-    sz = block_sum(sz, sh);
-    if (threadIdx.x == 0) {
-        out[3 * blockIdx.x + 0] = sx / d.n_cells;
-        out[3 * blockIdx.x + 1] = sy / d.n_cells;
-        out[3 * blockIdx.x + 2] = sz / d.n_cells;
-    }
-}
-
-__device__ __forceinline__ double wrap_pi(double x) {
-    // x + pi reduced into [0, 2 pi), minus pi
-    const double two_pi = 6.283185307179586476925286766559;
-    const double pi = 3.1415926535897932384626433832795;
-    double t = fmod(x + pi, two_pi);
-    if (t < 0.0) t += two_pi;
-    return t - pi;
-}
-
-// Vortex core position per disk, float64 (one workgroup per disk).
-// hint: per disk (x, y) in nm, NaN = no hint.
-__global__ __launch_bounds__(OBS_THREADS) void core_kernel(const DiskDesc* disks, const float* m_base,
-                                                           const double* hint, double a_nm, double cutoff_cells,
-                                                           double* out) {
-    __shared__ double sh[OBS_THREADS / 64];
-    __shared__ double s_score[OBS_THREADS / 64];
-    __shared__ int s_idx[OBS_THREADS / 64];
-    const int k = blockIdx.x;
-    const DiskDesc d = disks[k];
-    const int D = d.D, DD = D * D, Dm = D - 1;
-    const float* m = m_base + d.m_off;
-    const unsigned char* mask = d.mask;
-    const double half = (D - 1) / 2.0;
-    const double two_pi = 6.283185307179586476925286766559;
-    const double hx = hint[2 * k], hy = hint[2 * k + 1];
-    const bool use_hint = !(isnan(hx) || isnan(hy));
-
-    double best = -INFINITY;
-    int best_idx = 0x7fffffff;
-    int nplus = 0;
-    for (int p = threadIdx.x; p < Dm * Dm; p += OBS_THREADS) {
-        const int j = p / Dm, i = p - j * Dm;
-        const int ca = j * D + i, cb = ca + 1, cc = ca + D + 1, cd = ca + D;
-        if (!(mask[ca] && mask[cb] && mask[cc] && mask[cd])) continue;
-        const double fa = atan2((double)m[DD + ca], (double)m[ca]);
-        const double fb = atan2((double)m[DD + cb], (double)m[cb]);
-        const double fc = atan2((double)m[DD + cc], (double)m[cc]);
-        const double fd = atan2((double)m[DD + cd], (double)m[cd]);
-        const double s = wrap_pi(fb - fa) + wrap_pi(fc - fb) + wrap_pi(fd - fc) + wrap_pi(fa - fd);
-        if ((int)rint(s / two_pi) != 1) continue;
-        ++nplus;
-        double score;
-        const double cx = ((double)i - half) + 0.5, cy = ((double)j - half) + 0.5;
-        if (use_hint) {
-            const double ddx = cx - hx / a_nm, ddy = cy - hy / a_nm;
-            score = -(ddx * ddx + ddy * ddy);
-        } else {
-            const double za = m[2 * DD + ca], zb = m[2 * DD + cb], zc = m[2 * DD + cc], zd = m[2 * DD + cd];
-            score = za * za + zb * zb + zc * zc + zd * zd;
-        }
-        if (score > best || (score == best && p < best_idx)) {
-            best = score;
-            best_idx = p;
-        }
-    }
-    // argmax (higher score, then lower index) over the workgroup
-    for (int o = 32; o > 0; o >>= 1) {
-        const double os = __shfl_xor(best, o, 64);
-        const int oi = __shfl_xor(best_idx, o, 64);
-        if (os > best || (os == best && oi < best_idx)) {
-            best = os;
-            best_idx = oi;
-        }
-    }
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 0) {
-        s_score[wave] = best;
-        s_idx[wave] = best_idx;
-    }
-    const double np = block_sum((double)nplus, sh);
-    double bs = s_score[0];
-    int bi = s_idx[0];
-    for (int w = 1; w < OBS_THREADS / 64; ++w)
-        if (s_score[w] > bs || (s_score[w] == bs && s_idx[w] < bi)) {
-            bs = s_score[w];
-            bi = s_idx[w];
-        }
-    const bool found = np > 0.5;
-    double xv = NAN, yv = NAN;
-    if (found) {
-        const int j = bi / Dm, i = bi - j * Dm;
-        xv = ((double)i - half) + 0.5;
-        yv = ((double)j - half) + 0.5;
-    }
-    const double c2 = cutoff_cells * cutoff_cells;
-    double sw = 0.0, swx = 0.0, swy = 0.0;
-    for (int c = threadIdx.x; c < DD; c += OBS_THREADS) {
-        if (!mask[c]) continue;
-        const int j = c / D, i = c - j * D;
-        const double x = (double)i - half, y = (double)j - half;
-        if (found) {
-            const double ddx = x - xv, ddy = y - yv;
-            if (!(ddx * ddx + ddy * ddy < c2)) continue;
-        }
-        const double z = m[2 * DD + c];
-        const double w = z * z;
-        sw += w;
-        swx += w * x;
-        swy += w * y;
-    }
-    sw = block_sum(sw, sh);
-    swx = block_sum(swx, sh);
-    swy = block_sum(swy, sh);
-    if (threadIdx.x == 0) {
-        out[5 * k + 0] = swx / sw * a_nm;
-        out[5 * k + 1] = swy / sw * a_nm;
-        out[5 * k + 2] = xv * a_nm;
-        out[5 * k + 3] = yv * a_nm;
-        out[5 * k + 4] = np;
-    }
-}
-
-// Cotangent of the core position r_c (Sec. IV) with the plaquette r_v and the
-// cutoff set frozen at the values of `core` (the output of core_kernel for the
-// same state): r_c = sum w_i r_i / W, w_i = m_z,i^2, so
-// dL/dm_z,i += 2 m_z,i (rbar . (r_i - r_c)) / W for cells of the set.
-// mbar is accumulated (packed like the state); positions in nm.
-__global__ __launch_bounds__(OBS_THREADS) void core_vjp_kernel(const DiskDesc* disks, const float* m_base,
-                                                               const double* core, const double* rbar, double a_nm,
-                                                               double cutoff_cells, float* mbar_base) {
-    __shared__ double sh[OBS_THREADS / 64];
-    const int k = blockIdx.x;
-    const DiskDesc d = disks[k];
-    const int D = d.D, DD = D * D;
-    const float* m = m_base + d.m_off;
-    float* mbar = mbar_base + d.m_off;
-    const double half = (D - 1) / 2.0;
-    const bool found = core[5 * k + 4] > 0.5;
-    const double xv = core[5 * k + 2] / a_nm, yv = core[5 * k + 3] / a_nm;
-    const double xc = core[5 * k + 0], yc = core[5 * k + 1];
-    const double rx = rbar[2 * k], ry = rbar[2 * k + 1];
-    const double c2 = cutoff_cells * cutoff_cells;
-    auto in_set = [&](int c, double& x, double& y) {
-        if (!d.mask[c]) return false;
-        const int j = c / D, i = c - j * D;
-        x = (double)i - half;
-        y = (double)j - half;
-        if (!found) return true;
-        const double ddx = x - xv, ddy = y - yv;
-        return ddx * ddx + ddy * ddy < c2;
-    };
-    double W = 0.0;
-    for (int c = threadIdx.x; c < DD; c += OBS_THREADS) {
-        double x, y;
-        if (!in_set(c, x, y)) continue;
-        const double z = m[2 * DD + c];
-        W += z * z;
-    }
-    W = block_sum(W, sh);
-    for (int c = threadIdx.x; c < DD; c += OBS_THREADS) {
-        double x, y;
-        if (!in_set(c, x, y)) continue;
-        const double z = m[2 * DD + c];
-        const double g = 2.0 * z * (rx * (x * a_nm - xc) + ry * (y * a_nm - yc)) / W;
-        mbar[2 * DD + c] += (float)g;
-    }
+// Kernel pointer of the instance for (UG, RSEL, PMAX) of one mode.
+template <int MODE>
+const void* persistent_instance(int UG, int RSEL, int PMAX) {
+#define LLG_INST(ug, rs, pm)                                   \
+    if (UG == ug && RSEL == rs && PMAX == pm)                  \
+        return reinterpret_cast<const void*>(llg_persistent<ug, rs, MODE, pm>);
+    LLG_INST(1, 0, 256) LLG_INST(2, 0, 256) LLG_INST(4, 0, 256)
+    LLG_INST(1, 1, 256) LLG_INST(2, 1, 256) LLG_INST(4, 1, 256)
+    LLG_INST(1, 0, 512) LLG_INST(2, 0, 512) LLG_INST(4, 0, 512)
+    LLG_INST(1, 1, 512) LLG_INST(2, 1, 512) LLG_INST(4, 1, 512)
+#undef LLG_INST
+    return nullptr;
 }
 
 }  // namespace llg

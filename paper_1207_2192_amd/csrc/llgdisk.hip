@@ -18,7 +18,16 @@
 #include <vector>
 
 #include "../../include/llgdisk.h"
-#include "llg_kernels.hpp"
+#include "llg_aux_kernels.hpp"
+
+namespace llg {
+// persistent-kernel instances, one translation unit per mode (kernels_*.hip)
+const void* persistent_kernel_field(int UG, int RSEL, int PMAX);
+const void* persistent_kernel_rk4(int UG, int RSEL, int PMAX);
+const void* persistent_kernel_heun(int UG, int RSEL, int PMAX);
+const void* persistent_kernel_vjp(int UG, int RSEL, int PMAX);
+const void* persistent_kernel_relax(int UG, int RSEL, int PMAX);
+}  // namespace llg
 
 using namespace llg;
 
@@ -161,6 +170,7 @@ struct llg_disk_s {
     int* err_dev = nullptr;
     int UG = 1;                       // wavefront groups per workgroup of the persistent launch
     int RSEL = 0;                     // radix policy of the LDS transforms
+    int PMAX = 256;                   // largest FFT size of the handle's disks (kernel instance)
     std::vector<DiskDesc> desc;       // host copy of the descriptors
 
     ~llg_disk_s() {
@@ -191,26 +201,29 @@ struct llg_disk_s {
 
 namespace {
 
-const void* persistent_kernel(int UG, int RSEL) {
-    if (RSEL == 1) {
-        switch (UG) {
-            case 1: return reinterpret_cast<const void*>(llg_persistent<1, 1>);
-            case 2: return reinterpret_cast<const void*>(llg_persistent<2, 1>);
-            default: return reinterpret_cast<const void*>(llg_persistent<4, 1>);
-        }
-    }
-    switch (UG) {
-        case 1: return reinterpret_cast<const void*>(llg_persistent<1, 0>);
-        case 2: return reinterpret_cast<const void*>(llg_persistent<2, 0>);
-        default: return reinterpret_cast<const void*>(llg_persistent<4, 0>);
+const void* persistent_kernel(int mode, int UG, int RSEL, int PMAX) {
+    switch (mode) {
+        case MODE_RK4: return persistent_kernel_rk4(UG, RSEL, PMAX);
+        case MODE_HEUN: return persistent_kernel_heun(UG, RSEL, PMAX);
+        case MODE_RK4_VJP: return persistent_kernel_vjp(UG, RSEL, PMAX);
+        case MODE_RELAX: return persistent_kernel_relax(UG, RSEL, PMAX);
+        default: return persistent_kernel_field(UG, RSEL, PMAX);
     }
 }
 
-int max_coresident_workgroups(int UG, int RSEL, int* out) {
-    int dev = 0, ncu = 0, per_cu = 0;
+// Workgroups of the given shape that every mode's kernel can keep co-resident.
+int max_coresident_workgroups(int UG, int RSEL, int PMAX, int* out) {
+    int dev = 0, ncu = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel(UG, RSEL), WG_THREADS * UG, 0));
+    int per_cu = 1 << 30;
+    for (int mode : {MODE_DEMAG, MODE_RK4, MODE_HEUN, MODE_RK4_VJP, MODE_RELAX}) {
+        const void* k = persistent_kernel(mode, UG, RSEL, PMAX);
+        if (!k) return fail(LLG_EUNSUPPORTED, "no kernel instance for this launch shape");
+        int b = 0;
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k, WG_THREADS * UG, 0));
+        per_cu = std::min(per_cu, b);
+    }
     *out = ncu * per_cu;
     return 0;
 }
@@ -245,7 +258,7 @@ int plan(llg_disk h, int UG, int RSEL, const int* wg_per_disk) {
     if (RSEL != 0 && RSEL != 1) return fail(LLG_EINVAL, "radix policy must be 0 or 1");
     const int n = h->n;
     int cap = 0;
-    int rc = max_coresident_workgroups(UG, RSEL, &cap);
+    int rc = max_coresident_workgroups(UG, RSEL, h->PMAX, &cap);
     if (rc) return rc;
     std::vector<int> useful(n), G(n);
     std::vector<double> work(n);
@@ -418,6 +431,7 @@ int create(int n, const double* R_nm, const double* L_nm, double a_nm, const int
         h->L_nm.push_back(L_nm[k]);
         h->m_off.push_back(h->state_size);
         h->state_size += 3LL * D * D;
+        if (P > h->PMAX) h->PMAX = P;
     }
 
     // ---- per-disk workspaces
@@ -523,7 +537,7 @@ int launch(llg_disk h, int mode, float* m, float* out, long long nsteps, unsigne
     a.mode = mode;
     a.err = h->err_dev;
     void* args[] = {&a};
-    HIP_TRY(hipLaunchCooperativeKernel(persistent_kernel(h->UG, h->RSEL), dim3(h->n_wg), dim3(WG_THREADS * h->UG), args, 0,
+    HIP_TRY(hipLaunchCooperativeKernel(persistent_kernel(mode, h->UG, h->RSEL, h->PMAX), dim3(h->n_wg), dim3(WG_THREADS * h->UG), args, 0,
                                        st));
     return 0;
 }
