@@ -12,18 +12,23 @@ constexpr int WG_THREADS = 192;   // one group of three wavefronts: components x
 constexpr int MAX_UG = 4;         // wavefront groups per workgroup
 constexpr int MAX_P = 512;
 constexpr int MAX_R = 8;
-constexpr int LDS_FFT = 3 * 64 * MAX_R * 17 / 16;   // float2 per group: 3 waves x (64/Tf units) x padded P
+constexpr int LDS_FFT = 3 * 64 * MAX_R * 17 / 16 + 3 * 4 * 32;   // float2 per group: 3 waves x (64/Tf units) x padded P, bank skew
+// The row/column spectra are stored in blocks of SB rows: for each spectral
+// column kx the SB values of a block are contiguous (one 64-byte segment), so
+// a column pass reads whole segments and a row pass over SB/2 row pairs
+// writes whole segments.
+constexpr int SB = 8;
 
 // Per-disk descriptor (device memory, written once by the host).
 struct DiskDesc {
-    int D, P, H, Dp;          // box, FFT size, P/2+1, spectra row stride (D rounded up to even)
+    int D, P, H, Dp;          // box, FFT size, P/2+1, D rounded up to a multiple of SB
     int n_pairs, G, n_cells, k;  // row pairs, workgroups, masked cells, index in the batch
     long long m_off;          // float offset of this disk in a packed state
     float* ya;                // stage state A  [3][D][D]
     float* yb;                // stage state B  [3][D][D]
     float* acc;               // RK4 accumulator / Heun predictor increment / adjoint accumulator [3][D][D]
     float* aux;               // adjoint: direct part of the stage cotangent [3][D][D]
-    float2* S;                // row/column spectra [3][H][Dp]
+    float2* S;                // row/column spectra [3][Dp/SB][H][SB] (blocks of SB rows)
     const float* spec;        // kernel spectra quarter planes [4][H][H] (xx, yy, xy, zz) / P^2
     const unsigned char* mask;  // [D][D]
     const float2* tw;         // twiddles [P]
@@ -155,6 +160,32 @@ __device__ __forceinline__ float4 ld_sh4(const float2* p) {
 __device__ __forceinline__ void st_sh4(float2* p, float4 v) {
     st_sh2(p, make_float2(v.x, v.y));
     st_sh2(p + 1, make_float2(v.z, v.w));
+}
+
+// Wide accesses to the same shared buffers go through buffer instructions whose
+// cache-policy operand sets the same device-coherence bit (sc1) that the
+// device-scope atomics above carry; the buffer resource also bounds every
+// access to its range (out-of-range loads read 0, stores are dropped).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int CP_DEVICE = 16;   // cache policy: sc1
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, unsigned int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float bld1(__amdgpu_buffer_rsrc_t r, int off) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, CP_DEVICE));
+}
+__device__ __forceinline__ float2 bld2(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, CP_DEVICE));
+}
+__device__ __forceinline__ float4 bld4(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, CP_DEVICE));
+}
+__device__ __forceinline__ void bst2(__amdgpu_buffer_rsrc_t r, int off, float2 v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, CP_DEVICE);
+}
+__device__ __forceinline__ void bst4(__amdgpu_buffer_rsrc_t r, int off, float4 v) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, off, 0, CP_DEVICE);
 }
 
 // Wait until every store this wave issued has completed.

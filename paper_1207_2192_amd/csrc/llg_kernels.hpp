@@ -15,7 +15,8 @@
 //                  stage update, and the forward FFT along x of the new stage
 //                  state, unpacked into the row spectra for the next stage.
 //
-// The row spectra live in a [3][P/2+1][D] complex workspace per disk, so a
+// The row spectra live in a [3][Dp/SB][P/2+1][SB] complex workspace per disk
+// (blocks of SB rows, one 64-byte segment per spectral column and block), so a
 // field evaluation moves them through L2/HBM twice per phase pair.
 #pragma once
 #include "llg_device.hpp"
@@ -31,9 +32,19 @@ __device__ __forceinline__ bool in_disk(int j, int i, int D) {
     return x * x + y * y <= D * D;
 }
 
+// Rows staged in LDS per row iteration (the U row pairs and one row above and
+// below) and the padded length of a staged row (one zero margin on each side).
+template <int P, int R, int UG>
+struct RowTile {
+    static constexpr int U = UG * (64 / (P / R));
+    static constexpr int HR = 2 * U + 2;
+    static constexpr int HW = P / 2 + 2;
+    static constexpr int floats = 3 * HR * HW;
+};
+
 template <int P, int R, int UG, int MODE>
 __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, const DiskPrm& pr, int g,
-                                         float2* lds, float2* ltw) {
+                                         float2* lds, float2* ltw, float* halo) {
     constexpr int Tf = P / R;
     constexpr int U = UG * (64 / Tf);          // transforms per component in flight per workgroup
     constexpr int NT = WG_THREADS * UG;
@@ -44,16 +55,38 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     const int wave = wv % 3, grp = wv / 3;     // wave = component (or packed row) of the group
     const int u = grp * (64 / Tf) + lane / Tf, t = lane % Tf;
     constexpr int PS = padded_len<P>();
-    float2* const mybuf = lds + (wave * U + u) * PS;
-#define BUF(w, uu) (lds + ((w) * U + (uu)) * PS)
+    // Row-pass lanes come in groups of UQ row pairs that share one SB-row
+    // segment of the spectra; the UQ transform buffers of such a group start on
+    // different LDS banks.
+    constexpr int UQ = U < SB / 2 ? U : SB / 2;
+    constexpr int PSK = UQ == 1 ? PS : PS + (((32 / UQ - PS) % 32) + 32) % 32;
+    static_assert(3 * U * PSK <= LDS_FFT * UG, "transform buffers exceed the LDS reservation");
+    static_assert(SB == 8, "segment indexing below assumes SB = 8");
+    float2* const mybuf = lds + (wave * U + u) * PSK;
+#define BUF(w, uu) (lds + ((w) * U + (uu)) * PSK)
+    constexpr int HR = RowTile<P, R, UG>::HR, HW = RowTile<P, R, UG>::HW;
 
     for (int i = threadIdx.x; i < P; i += NT) ltw[i] = d.tw[i];
+    for (int r = threadIdx.x; r < 3 * HR; r += NT) {
+        halo[r * HW] = 0.f;
+        halo[r * HW + HW - 1] = 0.f;
+    }
     __syncthreads();
 
     float* const m = a.m + d.m_off;
     float* const out = a.out ? a.out + d.m_off : nullptr;
     const unsigned char* __restrict__ mask = d.mask;
     float2* __restrict__ S = d.S;
+    const int NJB = Dp >> 3;
+    const __amdgpu_buffer_rsrc_t Srs = make_rsrc(S, (unsigned)(3 * H * Dp) * 8u);
+    // byte offset of the spectrum of component c, column k, row j
+    auto soff = [&](int c, int k, int j) { return ((((c * NJB + (j >> 3)) * H + k) << 3) + (j & 7)) * 8; };
+    // row pass: item idx -> (row pair uu of the iteration, spectral column k)
+    auto pair_map = [&](int idx, int& uu, int& k) {
+        const int uq = idx % UQ, rest = idx / UQ;
+        k = rest % H;
+        uu = (rest / H) * UQ + uq;
+    };
     const int n_rb = (d.n_pairs + U - 1) / U;
     const int n_cb = (H + U - 1) / U;
     unsigned int epoch = 0;
@@ -99,7 +132,8 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         }
         fft_run<P, R, false>(v, mybuf, ltw, t);
         for (int idx = threadIdx.x; idx < U * H; idx += NT) {
-            const int uu = idx / H, k = idx - uu * H;
+            int uu, k;
+            pair_map(idx, uu, k);
             const int p = b * U + uu;
             if (p >= d.n_pairs) continue;
             const int j0 = 2 * p;
@@ -114,27 +148,27 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                                           0.5f * (A1.y + B1.y), -0.5f * (A1.x - B1.x));
             const float4 sz = make_float4(0.5f * (A2.x + B2.x), 0.5f * (A2.y - B2.y),
                                           0.5f * (A2.y + B2.y), -0.5f * (A2.x - B2.x));
-            st_sh4(S + (size_t)(0 * H + k) * Dp + j0, sx);
-            st_sh4(S + (size_t)(1 * H + k) * Dp + j0, sy);
-            st_sh4(S + (size_t)(2 * H + k) * Dp + j0, sz);
+            bst4(Srs, soff(0, k, j0), sx);
+            bst4(Srs, soff(1, k, j0), sy);
+            bst4(Srs, soff(2, k, j0), sz);
         }
         __syncthreads();
     };
 
     // ---- column kx: forward FFT along y, kernel multiply, inverse FFT along y
     constexpr int IM = (U * P + NT - 1) / NT;   // spectral points per thread in the multiply
-    auto column_phase = [&](int b) {
+    struct ColIn {
+        float2 v[R];        // this lane's column values
+        float kq[IM][4];    // kernel spectra at this thread's multiply points
+    };
+    auto col_load = [&](int b, ColIn& c) {
         const int kx = b * U + u;
         const bool valid = kx < H;
-        float2* col = S + (size_t)(wave * H + (valid ? kx : 0)) * Dp;
-        float2 v[R];
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const int i = t + j * Tf;
-            v[j] = (valid && i < D) ? ld_sh2(col + i) : make_float2(0.f, 0.f);
+            c.v[j] = (valid && i < D) ? bld2(Srs, soff(wave, kx, i)) : make_float2(0.f, 0.f);
         }
-        // kernel spectra for this thread's multiply points, loaded with the column
-        float kq4[IM][4];
 #pragma unroll
         for (int q = 0; q < IM; ++q) {
             const int idx = threadIdx.x + q * NT;
@@ -144,45 +178,79 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             const bool lo = ky <= P / 2;
             const int kq = lo ? ky : P - ky;
             const float* sp = d.spec + (size_t)(ok ? kxx : 0) * H + kq;
-            kq4[q][0] = ok ? sp[0] : 0.f;
-            kq4[q][1] = ok ? sp[H * H] : 0.f;
-            kq4[q][2] = ok ? (lo ? sp[2 * H * H] : -sp[2 * H * H]) : 0.f;
-            kq4[q][3] = ok ? sp[3 * H * H] : 0.f;
+            c.kq[q][0] = ok ? sp[0] : 0.f;
+            c.kq[q][1] = ok ? sp[H * H] : 0.f;
+            c.kq[q][2] = ok ? sp[2 * H * H] : 0.f;
+            c.kq[q][3] = ok ? sp[3 * H * H] : 0.f;
         }
-        fft_run<P, R, false>(v, mybuf, ltw, t);
+    };
+    auto col_compute = [&](int b, ColIn& c) {
+        const int kx = b * U + u;
+        const bool valid = kx < H;
+        fft_run<P, R, false>(c.v, mybuf, ltw, t);
 #pragma unroll
         for (int q = 0; q < IM; ++q) {
             const int idx = threadIdx.x + q * NT;
             if (idx >= U * P) continue;
             const int uu = idx / P, ky = idx - uu * P;
             if (b * U + uu >= H) continue;
-            const float Kxx = kq4[q][0], Kyy = kq4[q][1], Kxy = kq4[q][2], Kzz = kq4[q][3];
+            // K_xy is odd in ky: the quarter plane holds ky <= P/2
+            const float Kxx = c.kq[q][0], Kyy = c.kq[q][1], Kzz = c.kq[q][3];
+            const float Kxy = ky <= P / 2 ? c.kq[q][2] : -c.kq[q][2];
             const float2 mx = BUF(0, uu)[pad16(ky)], my = BUF(1, uu)[pad16(ky)], mz = BUF(2, uu)[pad16(ky)];
             BUF(0, uu)[pad16(ky)] = make_float2(Kxx * mx.x + Kxy * my.x, Kxx * mx.y + Kxy * my.y);
             BUF(1, uu)[pad16(ky)] = make_float2(Kxy * mx.x + Kyy * my.x, Kxy * mx.y + Kyy * my.y);
             BUF(2, uu)[pad16(ky)] = make_float2(Kzz * mz.x, Kzz * mz.y);
         }
         __syncthreads();
+        float2 v[R];
 #pragma unroll
         for (int j = 0; j < R; ++j) v[j] = mybuf[pad16(t + j * Tf)];
         fft_run<P, R, true>(v, mybuf, ltw, t);
-        if (valid)
-            for (int i = t; i < D; i += Tf) st_sh2(col + i, mybuf[pad16(i)]);
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int i = t + j * Tf;
+            if (valid && i < D) bst2(Srs, soff(wave, kx, i), mybuf[pad16(i)]);
+        }
         __syncthreads();
+    };
+    // all columns of this workgroup
+    auto column_pass = [&]() {
+        for (int b = g; b < n_cb; b += G) {
+            ColIn c;
+            col_load(b, c);
+            col_compute(b, c);
+        }
     };
 
     // ---- rebuild the full-length row spectra of a pair and transform back along x
-    auto row_inverse = [&](int b) {
-        for (int idx = threadIdx.x; idx < U * H; idx += NT) {
-            const int uu = idx / H, k = idx - uu * H;
+    constexpr int IS = (U * H + NT - 1) / NT;
+    struct SRow {
+        float4 x, y, z;
+    };
+    auto row_load = [&](int b, SRow (&sv)[IS]) {
+#pragma unroll
+        for (int q = 0; q < IS; ++q) {
+            const int idx = threadIdx.x + q * NT;
+            int uu, k;
+            pair_map(idx, uu, k);
             const int p = b * U + uu;
-            float4 sx = make_float4(0.f, 0.f, 0.f, 0.f), sy = sx, sz = sx;
-            if (p < d.n_pairs) {
-                const int j0 = 2 * p;
-                sx = ld_sh4(S + (size_t)(0 * H + k) * Dp + j0);
-                sy = ld_sh4(S + (size_t)(1 * H + k) * Dp + j0);
-                sz = ld_sh4(S + (size_t)(2 * H + k) * Dp + j0);
-            }
+            const bool ok = idx < U * H && p < d.n_pairs;
+            const int j0 = 2 * p;
+            const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+            sv[q].x = ok ? bld4(Srs, soff(0, k, j0)) : z4;
+            sv[q].y = ok ? bld4(Srs, soff(1, k, j0)) : z4;
+            sv[q].z = ok ? bld4(Srs, soff(2, k, j0)) : z4;
+        }
+    };
+    auto row_unpack_inverse = [&](const SRow (&sv)[IS]) {
+#pragma unroll
+        for (int q = 0; q < IS; ++q) {
+            const int idx = threadIdx.x + q * NT;
+            if (idx >= U * H) continue;
+            int uu, k;
+            pair_map(idx, uu, k);
+            const float4 sx = sv[q].x, sy = sv[q].y, sz = sv[q].z;
             // Hx + i Hy of each row, Hz(j0) + i Hz(j1); mirrored half from Hermitian symmetry
             BUF(0, uu)[pad16(k)] = make_float2(sx.x - sy.y, sx.y + sy.x);
             BUF(1, uu)[pad16(k)] = make_float2(sx.z - sy.w, sx.w + sy.z);
@@ -200,23 +268,55 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         for (int j = 0; j < R; ++j) v[j] = mybuf[pad16(t + j * Tf)];
         fft_run<P, R, true>(v, mybuf, ltw, t);
     };
+    auto row_inverse = [&](int b) {
+        SRow sv[IS];
+        row_load(b, sv);
+        row_unpack_inverse(sv);
+    };
+
+    // ---- stage state rows 2bU-1 .. 2bU+2U of iteration b into LDS (masked; zero
+    // outside the box), halo[(c*HR + rr)*HW + 1 + i] for row 2bU-1+rr and column i
+    constexpr int HC = P / 2;                    // staged columns (D <= P/2)
+    constexpr int IH = (3 * HR * HC + NT - 1) / NT;
+    auto halo_load = [&](int b, const float* Ys, float (&hv)[IH]) {
+        const __amdgpu_buffer_rsrc_t Yr = make_rsrc(Ys, (unsigned)(3 * DD) * 4u);
+#pragma unroll
+        for (int q = 0; q < IH; ++q) {
+            const int e = threadIdx.x + q * NT;
+            const int row = e / HC, i = e % HC;
+            const int c = row / HR, rr = row - c * HR;
+            const int j = 2 * b * U - 1 + rr;
+            const bool ok = row < 3 * HR && i < D && j >= 0 && j < D && in_disk(j, i, D);
+            hv[q] = ok ? bld1(Yr, (c * DD + j * D + i) * 4) : 0.f;
+        }
+    };
+    auto halo_store = [&](const float (&hv)[IH]) {
+#pragma unroll
+        for (int q = 0; q < IH; ++q) {
+            const int e = threadIdx.x + q * NT;
+            const int row = e / HC, i = e % HC;
+            if (row < 3 * HR) halo[row * HW + 1 + i] = hv[q];
+        }
+    };
 
     double e_ex = 0.0, e_dm = 0.0, e_ext = 0.0;
     const float hxf = pr.hx, hyf = pr.hy, hzf = pr.hz, cf = pr.c, al = pr.alpha, dt = pr.dtau;
 
     // ---- per-cell work after the inverse transforms; new stage state back into LDS
     // stage s of step n; Ys = state whose field is in LDS; Yn = where the next stage state goes.
-    // Every global value a column of the row pair needs is gathered first with
-    // independent loads (one memory latency), then both cells are updated.
+    // The stage state around the row pairs comes from LDS (staged rows); the
+    // step's start state and the accumulator of the two cells of a column are
+    // loaded into registers before the row spectra, so that all of the
+    // iteration's loads share one memory latency.
     const bool need_y0 = (mode == MODE_RK4) || (mode == MODE_HEUN);
     float* const recd = a.rec ? a.rec + (size_t)a.nsteps * 8 * (size_t)d.m_off : nullptr;
     // Gathered values of one column of a row pair (registers).
     struct Gath {
-        float col[4][3], lft[2][3], rgt[2][3], y0[2][3], ac[2][3];
+        float y0[2][3], ac[2][3];
     };
     constexpr int IC = (U * (P / 2) + NT - 1) / NT;   // cell-update items per thread (D <= P/2)
     Gath gv[IC];
-    auto gather = [&](int b, int s, const float* Ys) {
+    auto gather = [&](int b, int s) {
         const bool need_acc = (mode == MODE_RK4 && s > 0) || (mode == MODE_HEUN && s == 1);
 #pragma unroll
         for (int q = 0; q < IC; ++q) {
@@ -227,23 +327,12 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             const int j0 = 2 * p;
             Gath& G_ = gv[q];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int j = j0 - 1 + r;
-                const bool ok = live && j >= 0 && j < D && in_disk(j, i, D);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) G_.col[r][c] = ok ? ld_sh(Ys + c * DD + j * D + i) : 0.f;
-            }
-#pragma unroll
             for (int r = 0; r < 2; ++r) {
                 const int j = j0 + r;
-                const bool okl = live && j < D && i > 0 && in_disk(j, i - 1, D);
-                const bool okr = live && j < D && i + 1 < D && in_disk(j, i + 1, D);
                 const bool okc = live && j < D && in_disk(j, i, D);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const int cell = c * DD + j * D + i;
-                    G_.lft[r][c] = okl ? ld_sh(Ys + cell - 1) : 0.f;
-                    G_.rgt[r][c] = okr ? ld_sh(Ys + cell + 1) : 0.f;
                     G_.y0[r][c] = (need_y0 && okc) ? ld_sh(m + cell) : 0.f;
                     G_.ac[r][c] = (need_acc && okc) ? d.acc[cell] : 0.f;
                 }
@@ -259,9 +348,18 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             const int p = b * U + uu;
             if (p >= d.n_pairs) continue;
             const int j0 = 2 * p;
-            const float (&col)[4][3] = gv[q].col;
-            const float (&lft)[2][3] = gv[q].lft;
-            const float (&rgt)[2][3] = gv[q].rgt;
+            float col[4][3], lft[2][3], rgt[2][3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float* hr = halo + (c * HR + 2 * uu) * HW + 1 + i;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) col[r][c] = hr[r * HW];
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    lft[r][c] = hr[(r + 1) * HW - 1];
+                    rgt[r][c] = hr[(r + 1) * HW + 1];
+                }
+            }
             const float (&y0)[2][3] = gv[q].y0;
             const float (&ac)[2][3] = gv[q].ac;
             const float2 hz2 = BUF(2, uu)[pad16(i)];
@@ -651,7 +749,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         float* nxt = d.ya;
         __shared__ double red8[3 * MAX_UG][8];
         for (; sweep < a.nsteps; ++sweep) {
-            for (int b = g; b < n_cb; b += G) column_phase(b);
+            column_pass();
             if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
             for (int q = 0; q < 8; ++q) rq[q] = 0.0;
             for (int b = g; b < n_rb; b += G) {
@@ -736,7 +834,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             }
             if (k == K) break;
             if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
-            for (int b = g; b < n_cb; b += G) column_phase(b);
+            column_pass();
             if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
         }
         write_partials(e_ex, e_dm, 0.0);
@@ -750,14 +848,22 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     }
     if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
 
+    // one row iteration of a field evaluation: issue every load, then stage, transform and update
+    auto row_step = [&](int b, int s, long long n, const float* Ys, float* Yn) {
+        float hv[IH];
+        SRow sv[IS];
+        halo_load(b, Ys, hv);
+        gather(b, s);
+        row_load(b, sv);
+        halo_store(hv);
+        row_unpack_inverse(sv);
+        cell_update(b, s, n, Yn);
+    };
+
     if constexpr (MODE == MODE_DEMAG) {
-        for (int b = g; b < n_cb; b += G) column_phase(b);
+        column_pass();
         if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
-        for (int b = g; b < n_rb; b += G) {
-            gather(b, 0, m);
-            row_inverse(b);
-            cell_update(b, 0, 0, nullptr);
-        }
+        for (int b = g; b < n_rb; b += G) row_step(b, 0, 0, m, nullptr);
         if (mode == MODE_ENERGY) write_partials(e_ex, e_dm, e_ext);
         return;
     }
@@ -766,7 +872,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     constexpr int nst = (MODE == MODE_RK4) ? 4 : 2;
     for (long long n = 0; n < a.nsteps; ++n) {
         for (int s = 0; s < nst; ++s) {
-            for (int b = g; b < n_cb; b += G) column_phase(b);
+            column_pass();
             if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
             const bool last = (n == a.nsteps - 1) && (s == nst - 1);
             const float* Ys;
@@ -779,9 +885,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                 Yn = (s == 0) ? d.ya : m;
             }
             for (int b = g; b < n_rb; b += G) {
-                gather(b, s, Ys);
-                row_inverse(b);
-                cell_update(b, s, n, Yn);
+                row_step(b, s, n, Ys, Yn);
                 if (!last) row_forward_store(b);
             }
             if (!last && !group_barrier(d.bar, ++epoch * G, G, a.err)) return;
@@ -804,10 +908,21 @@ struct Radix {
 // largest FFT size PMAX of the handle): each instance carries only the code
 // and registers of its own path.  MODE_DEMAG stands for the field kernel
 // (demag, rhs and energy, chosen at run time).
+template <int UG, int RSEL>
+constexpr int halo_floats(int PMAX) {
+    int n = RowTile<64, Radix<64, RSEL>::value, UG>::floats;
+    n = n > RowTile<128, Radix<128, RSEL>::value, UG>::floats ? n : RowTile<128, Radix<128, RSEL>::value, UG>::floats;
+    n = n > RowTile<256, Radix<256, RSEL>::value, UG>::floats ? n : RowTile<256, Radix<256, RSEL>::value, UG>::floats;
+    if (PMAX >= 512)
+        n = n > RowTile<512, Radix<512, RSEL>::value, UG>::floats ? n : RowTile<512, Radix<512, RSEL>::value, UG>::floats;
+    return n;
+}
+
 template <int UG, int RSEL, int MODE, int PMAX>
 __global__ __launch_bounds__(WG_THREADS* UG) void llg_persistent(KArgs a) {
     __shared__ float2 lds[LDS_FFT * UG];
     __shared__ float2 ltw[MAX_P];
+    __shared__ float halo[halo_floats<UG, RSEL>(PMAX)];
     const int wg = blockIdx.x;
     const int di = a.wg2disk[wg];
     if (di < 0) return;
@@ -815,11 +930,11 @@ __global__ __launch_bounds__(WG_THREADS* UG) void llg_persistent(KArgs a) {
     const DiskDesc d = a.disks[di];
     const DiskPrm pr = a.prm[di];
     switch (d.P) {
-        case 64: run_disk<64, Radix<64, RSEL>::value, UG, MODE>(a, d, pr, g, lds, ltw); break;
-        case 128: run_disk<128, Radix<128, RSEL>::value, UG, MODE>(a, d, pr, g, lds, ltw); break;
-        case 256: run_disk<256, Radix<256, RSEL>::value, UG, MODE>(a, d, pr, g, lds, ltw); break;
+        case 64: run_disk<64, Radix<64, RSEL>::value, UG, MODE>(a, d, pr, g, lds, ltw, halo); break;
+        case 128: run_disk<128, Radix<128, RSEL>::value, UG, MODE>(a, d, pr, g, lds, ltw, halo); break;
+        case 256: run_disk<256, Radix<256, RSEL>::value, UG, MODE>(a, d, pr, g, lds, ltw, halo); break;
         case 512:
-            if constexpr (PMAX >= 512) run_disk<512, Radix<512, RSEL>::value, UG, MODE>(a, d, pr, g, lds, ltw);
+            if constexpr (PMAX >= 512) run_disk<512, Radix<512, RSEL>::value, UG, MODE>(a, d, pr, g, lds, ltw, halo);
             break;
         default: break;
     }

@@ -447,7 +447,7 @@ int create(int n, const double* R_nm, const double* L_nm, double a_nm, const int
         d.D = h->D[k];
         d.P = h->P[k];
         d.H = d.P / 2 + 1;
-        d.Dp = d.D + (d.D & 1);
+        d.Dp = (d.D + SB - 1) / SB * SB;
         d.n_pairs = (d.D + 1) / 2;
         d.n_cells = g.n_cells;
         d.k = k;
