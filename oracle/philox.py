@@ -9,13 +9,17 @@ takes the high and low halves of the 128-bit products, and mixes them with
 the other two words and the key; the key is bumped by two Weyl constants
 between rounds.
 
-Noise layout (shared with the HIP library): for time step ``step``, replica
-``replica`` and box cell n = iy*D + ix, the block counter is
-(step, n, replica, 0) and the key is (seed, 0).  The four 64-bit outputs
-x0..x3 become uniforms u_k = ((x_k >> 40) + 0.5) * 2^-24 (exact in FP32) and
-three standard normals by Box-Muller:
-  w_x = sqrt(-2 ln u0) cos(2 pi u1),  w_y = sqrt(-2 ln u0) sin(2 pi u1),
-  w_z = sqrt(-2 ln u2) cos(2 pi u3).
+Noise layout (shared with the HIP library): the two cells (2p, ix) and
+(2p+1, ix) of row pair p and column ix draw from one block.  For time step
+``step`` and replica ``replica`` the block counter is (step, p*D + ix,
+replica, 0) and the key is (seed, 0).  Each 64-bit output x_k gives two
+uniforms, from its top 24 bits and from bits 8..31:
+  hi(x) = ((x >> 40) + 0.5) * 2^-24,  lo(x) = (((x >> 8) mod 2^24) + 0.5) * 2^-24
+(both exact in FP32), and U = (hi x0, lo x0, hi x1, lo x1, hi x2, lo x2)
+gives six standard normals by Box-Muller,
+  n_{2k} = sqrt(-2 ln U_{2k}) cos(2 pi U_{2k+1}),
+  n_{2k+1} = sqrt(-2 ln U_{2k}) sin(2 pi U_{2k+1}),   k = 0, 1, 2;
+cell (2p, ix) takes (n0, n1, n2) and cell (2p+1, ix) takes (n3, n4, n5).
 """
 from __future__ import annotations
 
@@ -68,6 +72,11 @@ def uniforms24(x: np.ndarray) -> np.ndarray:
     return ((x >> np.uint64(40)).astype(np.float64) + 0.5) * 2.0 ** -24
 
 
+def uniforms24_low(x: np.ndarray) -> np.ndarray:
+    """Bits 8..31 of a uint64 as a uniform in (0, 1), in float64."""
+    return (((x >> np.uint64(8)) & np.uint64(0xFFFFFF)).astype(np.float64) + 0.5) * 2.0 ** -24
+
+
 def gaussian_field(seed: int, step: int, replica, D: int) -> np.ndarray:
     """Standard-normal noise of every box cell.
 
@@ -76,13 +85,16 @@ def gaussian_field(seed: int, step: int, replica, D: int) -> np.ndarray:
     """
     scalar = np.ndim(replica) == 0
     reps = np.atleast_1d(np.asarray(replica, dtype=np.uint64))[:, None]
-    n = np.arange(D * D, dtype=np.uint64)[None, :]
-    x0, x1, x2, x3 = philox4x64_10((np.uint64(step), n, reps, np.uint64(0)),
-                                   (np.uint64(seed), np.uint64(0)))
-    u0, u1, u2, u3 = (uniforms24(x) for x in (x0, x1, x2, x3))
-    r01 = np.sqrt(-2.0 * np.log(u0))
-    r23 = np.sqrt(-2.0 * np.log(u2))
-    w = np.stack([r01 * np.cos(2 * np.pi * u1), r01 * np.sin(2 * np.pi * u1),
-                  r23 * np.cos(2 * np.pi * u3)], axis=1)          # [B, 3, D*D]
-    w = w.reshape(-1, 3, D, D)
+    n_pairs = (D + 1) // 2
+    q = np.arange(n_pairs * D, dtype=np.uint64)[None, :]          # q = p*D + ix
+    x0, x1, x2, _ = philox4x64_10((np.uint64(step), q, reps, np.uint64(0)),
+                                  (np.uint64(seed), np.uint64(0)))
+    U = [f(x) for x in (x0, x1, x2) for f in (uniforms24, uniforms24_low)]
+    n = []
+    for k in range(3):
+        r = np.sqrt(-2.0 * np.log(U[2 * k]))
+        n += [r * np.cos(2 * np.pi * U[2 * k + 1]), r * np.sin(2 * np.pi * U[2 * k + 1])]
+    even = np.stack(n[:3], axis=1).reshape(-1, 3, n_pairs, D)    # cells (2p, ix)
+    odd = np.stack(n[3:], axis=1).reshape(-1, 3, n_pairs, D)     # cells (2p+1, ix)
+    w = np.stack([even, odd], axis=3).reshape(-1, 3, 2 * n_pairs, D)[:, :, :D]
     return w[0] if scalar else w

@@ -1,8 +1,9 @@
 // Stockham radix-R FFT of length P held in LDS, one transform per group of
-// P/R lanes.  Written for gfx950: a workgroup runs three wavefronts (one per
-// field component or packed row pair) that step through identical stage
-// schedules, so every stage boundary is a workgroup barrier and LDS holds one
-// P-point buffer per transform.
+// P/R lanes of one wavefront.  A transform never leaves its wavefront, and the
+// LDS operations of a wavefront are performed in issue order, so the stages
+// are separated by wavefront-scope fences (ordering for the compiler, no
+// instruction); only the end of a transform is a workgroup barrier, because
+// the callers then read the results across wavefronts.
 //
 // Forward: X[k] = sum_n x[n] exp(-2 pi i n k / P); inverse uses +i and is not
 // normalised.  Twiddles come from a table W[e] = exp(-2 pi i e / P) computed in
@@ -82,6 +83,30 @@ __device__ __forceinline__ void dftR(float2* x) {
 
 constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 
+// Order this lane's LDS accesses against those of the other lanes of its wavefront.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Powers w^1 .. w^(R-1) of one table twiddle by products of powers (at most
+// three roundings deep for R = 8), so that a stage reads one twiddle from LDS
+// instead of R-1.
+template <int R>
+__device__ __forceinline__ void twiddle_powers(float2 w1, float2 (&w)[R]) {
+    w[1] = w1;
+    if constexpr (R >= 4) {
+        w[2] = cmul(w1, w1);
+        w[3] = cmul(w1, w[2]);
+    }
+    if constexpr (R == 8) {
+        w[4] = cmul(w[2], w[2]);
+        w[5] = cmul(w1, w[4]);
+        w[6] = cmul(w[2], w[4]);
+        w[7] = cmul(w[3], w[4]);
+    }
+}
+
 // LDS layout of a transform buffer: one padding slot after every 16 complex
 // values, so that the strided Stockham writes of a 16-lane group land in 16
 // different bank pairs.
@@ -92,8 +117,9 @@ constexpr int padded_len() { return P + P / 16; }
 // One length-P transform by the lanes t = 0 .. P/R-1 of a lane group.
 // On entry v[j] = x[t + j*(P/R)].  On exit buf holds X in natural order
 // (element e at buf[pad16(e)]).  buf may alias the input storage; tw is the P-entry twiddle table.
-// Every lane of the workgroup must call this the same number of times
-// (it contains workgroup barriers).
+// buf is touched only by the lanes of this transform until the closing
+// workgroup barrier, so every lane of the workgroup must call this the same
+// number of times.
 template <int P, int R, bool INV>
 __device__ __forceinline__ void fft_run(float2 (&v)[R], float2* buf, const float2* tw, int t) {
     constexpr int Tf = P / R;
@@ -108,20 +134,21 @@ __device__ __forceinline__ void fft_run(float2 (&v)[R], float2* buf, const float
 #pragma unroll
             for (int j = 0; j < R; ++j) v[j] = buf[pad16(t + j * Tf)];
             const int kk = t & (Ns - 1);
-            const int stp = kk * (P / (Ns * R));
+            float2 w[R];
+            twiddle_powers<R>(tw[kk * (P / (Ns * R))], w);
 #pragma unroll
-            for (int j = 1; j < R; ++j) {
-                const float2 w = tw[(j * stp) & (P - 1)];
-                v[j] = INV ? cmulc(v[j], w) : cmul(v[j], w);
-            }
+            for (int j = 1; j < R; ++j) v[j] = INV ? cmulc(v[j], w[j]) : cmul(v[j], w[j]);
         }
         dftR<R, INV>(v);
         const int kk = t & (Ns - 1);
         const int base = (t - kk) * R + kk;
-        __syncthreads();
+        wave_sync();
 #pragma unroll
         for (int j = 0; j < R; ++j) buf[pad16(base + j * Ns)] = v[j];
-        __syncthreads();
+        if (REM == 1 && s == NFULL - 1)
+            __syncthreads();
+        else
+            wave_sync();
         Ns *= R;
     }
     if constexpr (REM > 1) {
@@ -131,19 +158,17 @@ __device__ __forceinline__ void fft_run(float2 (&v)[R], float2* buf, const float
         for (int q = 0; q < NB; ++q) {
             const int k = t + q * Tf;
             const int kk = k & (Ns - 1);
-            const int stp = kk * (P / (Ns * REM));
+            float2 w[REM];
+            twiddle_powers<REM>(tw[kk * (P / (Ns * REM))], w);
 #pragma unroll
             for (int j = 0; j < REM; ++j) {
                 float2 x = buf[pad16(k + j * (P / REM))];
-                if (j > 0) {
-                    const float2 w = tw[(j * stp) & (P - 1)];
-                    x = INV ? cmulc(x, w) : cmul(x, w);
-                }
+                if (j > 0) x = INV ? cmulc(x, w[j]) : cmul(x, w[j]);
                 u[q * REM + j] = x;
             }
             dftR<REM, INV>(u + q * REM);
         }
-        __syncthreads();
+        wave_sync();
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
             const int k = t + q * Tf;

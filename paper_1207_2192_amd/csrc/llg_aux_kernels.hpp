@@ -54,7 +54,13 @@ __global__ void noise_kernel(const DiskDesc* disks, int n, float* w, unsigned lo
     float* out = w + d.m_off;
     for (int cell = blockIdx.x * blockDim.x + threadIdx.x; cell < DD; cell += gridDim.x * blockDim.x) {
         float3 v = make_float3(0.f, 0.f, 0.f);
-        if (d.mask[cell]) v = thermal_normals(seed, step, (unsigned long long)cell, (unsigned long long)(replica0 + d.k));
+        if (d.mask[cell]) {
+            const int j = cell / d.D, i = cell - j * d.D;
+            float3 ev, od;
+            thermal_normals_pair(seed, step, (unsigned long long)((j >> 1) * d.D + i),
+                                 (unsigned long long)(replica0 + d.k), ev, od);
+            v = (j & 1) ? od : ev;
+        }
         out[cell] = v.x;
         out[DD + cell] = v.y;
         out[2 * DD + cell] = v.z;

@@ -100,22 +100,32 @@ __device__ __forceinline__ void philox4x64_10(uint64_t& c0, uint64_t& c1, uint64
     }
 }
 
+// Uniforms in (0, 1) from the top 24 bits and from bits 8..31 of a 64-bit word.
 __device__ __forceinline__ float u24(uint64_t x) {
     return ((float)(uint32_t)(x >> 40) + 0.5f) * 5.9604644775390625e-08f;  // 2^-24
 }
+__device__ __forceinline__ float u24lo(uint64_t x) {
+    return ((float)(((uint32_t)x) >> 8) + 0.5f) * 5.9604644775390625e-08f;
+}
 
-// Three standard normals for (step, cell, replica) under `seed`.
-__device__ __forceinline__ float3 thermal_normals(unsigned long long seed, unsigned long long step,
-                                                  unsigned long long cell, unsigned long long replica) {
-    uint64_t c0 = step, c1 = cell, c2 = replica, c3 = 0;
+// Six standard normals for the two cells (2p, ix), (2p+1, ix) of row pair p:
+// block counter (step, p*D + ix, replica, 0), key (seed, 0); the three words
+// x0..x2 give the uniforms (hi x0, lo x0, hi x1, lo x1, hi x2, lo x2) and three
+// Box-Muller pairs; the even row takes normals 0..2, the odd row 3..5.
+__device__ __forceinline__ void thermal_normals_pair(unsigned long long seed, unsigned long long step,
+                                                     unsigned long long q, unsigned long long replica,
+                                                     float3& even, float3& odd) {
+    uint64_t c0 = step, c1 = q, c2 = replica, c3 = 0;
     philox4x64_10(c0, c1, c2, c3, seed, 0ull);
-    const float u0 = u24(c0), u1 = u24(c1), u2 = u24(c2), u3 = u24(c3);
-    const float r01 = sqrtf(-2.0f * logf(u0));
-    const float r23 = sqrtf(-2.0f * logf(u2));
-    float s1, c1f, s3, c3f;
-    sincospif(2.0f * u1, &s1, &c1f);
-    sincospif(2.0f * u3, &s3, &c3f);
-    return make_float3(r01 * c1f, r01 * s1, r23 * c3f);
+    const float ra = sqrtf(-2.0f * logf(u24(c0)));
+    const float rb = sqrtf(-2.0f * logf(u24(c1)));
+    const float rc = sqrtf(-2.0f * logf(u24(c2)));
+    float sa, ca, sb, cb, sc, cc;
+    sincospif(2.0f * u24lo(c0), &sa, &ca);
+    sincospif(2.0f * u24lo(c1), &sb, &cb);
+    sincospif(2.0f * u24lo(c2), &sc, &cc);
+    even = make_float3(ra * ca, ra * sa, rb * cb);
+    odd = make_float3(rb * sb, rc * cc, rc * sc);
 }
 
 // ---------------------------------------------------------------- shared buffers

@@ -364,6 +364,10 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             const float (&ac)[2][3] = gv[q].ac;
             const float2 hz2 = BUF(2, uu)[pad16(i)];
             float nxt[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+            float3 wn[2];
+            if (mode == MODE_HEUN && (in_disk(j0, i, D) || (j0 + 1 < D && in_disk(j0 + 1, i, D))))
+                thermal_normals_pair(a.seed, a.step0 + (unsigned long long)n, (unsigned long long)(p * D + i),
+                                     (unsigned long long)(a.replica0 + d.k), wn[0], wn[1]);
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
                 const int j = j0 + r;
@@ -443,8 +447,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                         }
                     }
                 } else if (in) {  // MODE_HEUN
-                    const float3 w = thermal_normals(a.seed, a.step0 + (unsigned long long)n, (unsigned long long)cell,
-                                                     (unsigned long long)(a.replica0 + d.k));
+                    const float3 w = wn[r];
                     const float sg = pr.sigma;
                     const float gx = bx * dt + sg * w.x, gy = by * dt + sg * w.y, gz = bz * dt + sg * w.z;
                     const float px = my * gz - mz * gy, py = mz * gx - mx * gz, pz = mx * gy - my * gx;

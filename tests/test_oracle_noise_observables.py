@@ -11,7 +11,7 @@ import llg_inputs as li
 from oracle import Disk, Params
 from oracle.observables import (energy, energy_from_exchange_field, mean_m, plaquette_windings,
                                 vortex_core_position)
-from oracle.philox import gaussian_field, philox4x64_10, uniforms24
+from oracle.philox import gaussian_field, philox4x64_10, uniforms24, uniforms24_low
 
 C_PY = 0.14298555
 LAM_NM = 5.28906
@@ -37,6 +37,9 @@ def test_uniforms_exact_and_open():
     u = uniforms24(x)
     assert u[0] == 0.5 * 2**-24 and u[1] == 1 - 0.5 * 2**-24 and 0 < u.min() and u.max() < 1
     assert np.all(u * 2**25 == np.round(u * 2**25))   # multiples of 2^-25: exact in FP32
+    v = uniforms24_low(np.array([0, 2**64 - 1, 0xFF, 0x1_0000_0100, 2**32 - 256], dtype=np.uint64))
+    assert v[0] == 0.5 * 2**-24 and v[1] == 1 - 0.5 * 2**-24 and v[2] == v[0]      # bits 0..7 are dropped
+    assert v[3] == 1.5 * 2**-24 and v[4] == v[1]                                   # bit 8 is the lowest kept
 
 
 def test_normals_are_standard_and_independent():
@@ -47,6 +50,14 @@ def test_normals_are_standard_and_independent():
     cxy = np.corrcoef(w[:, 0].ravel(), w[:, 1].ravel())[0, 1]
     cxz = np.corrcoef(w[:, 0].ravel(), w[:, 2].ravel())[0, 1]
     assert abs(cxy) < 0.02 and abs(cxz) < 0.02
+    # the two rows of a pair share a block but not its normals
+    ce = np.corrcoef(w[:, :, 0::2].ravel(), w[:, :, 1::2].ravel())[0, 1]
+    assert abs(ce) < 0.02
+    for c in range(3):
+        assert abs(w[:, c].mean()) < 0.02 and abs(w[:, c].std() - 1) < 0.02
+    # an odd box keeps its last row
+    w7 = gaussian_field(3, 2, 0, 7)
+    assert w7.shape == (3, 7, 7) and np.all(np.isfinite(w7)) and np.abs(w7[:, 6]).sum() > 0
     # different steps / replicas give unrelated noise
     a = gaussian_field(1, 0, 0, 16).ravel()
     b = gaussian_field(1, 1, 0, 16).ravel()
