@@ -5,9 +5,8 @@ Default workload: a Permalloy disk R = 100 nm, L = 20 nm on a = 2 nm cells
 dtau = 0.04, started from a vortex displaced to X = (10 nm, 0).  One step is a
 full RK4 step (four field evaluations, each with the zero-padded FFT demag).
 
-Prints one JSON line (see the README of the contract in the design doc) with the
-roofline of the persistent kernel and the FP64 CPU oracle timed on a bounded
-sample of the same workload.
+Prints one JSON line with the roofline of the persistent kernel and the FP64
+CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -25,7 +24,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 C_PY = 0.14298555          # a^2/lambda_ex^2, Permalloy, a = 2 nm
 KERNEL_SOURCES = ["paper_1207_2192_amd/csrc/llg_kernels.hpp", "paper_1207_2192_amd/csrc/fft_lds.hpp",
-                  "paper_1207_2192_amd/csrc/llg_device.hpp"]
+                  "paper_1207_2192_amd/csrc/llg_device.hpp", "paper_1207_2192_amd/csrc/kernels_rk4.hip",
+                  "paper_1207_2192_amd/csrc/kernels_heun.hip"]
 
 
 def kernel_hash() -> str:

@@ -201,6 +201,18 @@ __device__ __forceinline__ void bst4(__amdgpu_buffer_rsrc_t r, int off, float4 v
 // Wait until every store this wave issued has completed.
 __device__ __forceinline__ void drain_stores() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
+// The thread index, optionally passed through an empty asm statement: index
+// arithmetic derived from it is then recomputed where it is used inside the
+// persistent step loop, instead of being hoisted out of the loop and held in
+// registers for the whole launch (which caps the resident wavefronts).  Worth
+// it only where register pressure, not latency, limits the kernel.
+template <bool OPAQUE>
+__device__ __forceinline__ int tid() {
+    int x = threadIdx.x;
+    if constexpr (OPAQUE) asm volatile("" : "+v"(x));
+    return x;
+}
+
 // ---------------------------------------------------------------- group barrier
 // All workgroups that step one disk meet here.  The counter only grows during
 // a launch (it is cleared before each launch); `target` = epoch * G.  A wait

@@ -47,11 +47,13 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                                          float2* lds, float2* ltw, float* halo) {
     constexpr int Tf = P / R;
     constexpr int U = UG * (64 / Tf);          // transforms per component in flight per workgroup
+    // the adjoint keeps many values per cell in registers: recompute its index arithmetic
+    constexpr bool OPQ = MODE == MODE_RK4_VJP;
     constexpr int NT = WG_THREADS * UG;
     constexpr int H = P / 2 + 1;
     const int D = d.D, Dp = d.Dp, G = d.G;
     const int DD = D * D;
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wv = tid<OPQ>() >> 6, lane = tid<OPQ>() & 63;
     const int wave = wv % 3, grp = wv / 3;     // wave = component (or packed row) of the group
     const int u = grp * (64 / Tf) + lane / Tf, t = lane % Tf;
     constexpr int PS = padded_len<P>();
@@ -66,8 +68,8 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
 #define BUF(w, uu) (lds + ((w) * U + (uu)) * PSK)
     constexpr int HR = RowTile<P, R, UG>::HR, HW = RowTile<P, R, UG>::HW;
 
-    for (int i = threadIdx.x; i < P; i += NT) ltw[i] = d.tw[i];
-    for (int r = threadIdx.x; r < 3 * HR; r += NT) {
+    for (int i = tid<OPQ>(); i < P; i += NT) ltw[i] = d.tw[i];
+    for (int r = tid<OPQ>(); r < 3 * HR; r += NT) {
         halo[r * HW] = 0.f;
         halo[r * HW + HW - 1] = 0.f;
     }
@@ -95,7 +97,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
 
     // ---- packed rows of a state into LDS (masked), columns [0, D)
     auto load_state_rows = [&](int b, const float* src) {
-        for (int idx = threadIdx.x; idx < U * D; idx += NT) {
+        for (int idx = tid<OPQ>(); idx < U * D; idx += NT) {
             const int uu = idx / D, i = idx - uu * D;
             const int p = b * U + uu, j0 = 2 * p, j1 = j0 + 1;
             float x0 = 0.f, y0 = 0.f, z0 = 0.f, x1 = 0.f, y1 = 0.f, z1 = 0.f;
@@ -131,7 +133,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             v[j] = (i < D) ? mybuf[pad16(i)] : make_float2(0.f, 0.f);
         }
         fft_run<P, R, false>(v, mybuf, ltw, t);
-        for (int idx = threadIdx.x; idx < U * H; idx += NT) {
+        for (int idx = tid<OPQ>(); idx < U * H; idx += NT) {
             int uu, k;
             pair_map(idx, uu, k);
             const int p = b * U + uu;
@@ -171,7 +173,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         }
 #pragma unroll
         for (int q = 0; q < IM; ++q) {
-            const int idx = threadIdx.x + q * NT;
+            const int idx = tid<OPQ>() + q * NT;
             const int uu = idx / P, ky = idx - uu * P;
             const int kxx = b * U + uu;
             const bool ok = idx < U * P && kxx < H;
@@ -190,7 +192,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         fft_run<P, R, false>(c.v, mybuf, ltw, t);
 #pragma unroll
         for (int q = 0; q < IM; ++q) {
-            const int idx = threadIdx.x + q * NT;
+            const int idx = tid<OPQ>() + q * NT;
             if (idx >= U * P) continue;
             const int uu = idx / P, ky = idx - uu * P;
             if (b * U + uu >= H) continue;
@@ -231,7 +233,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     auto row_load = [&](int b, SRow (&sv)[IS]) {
 #pragma unroll
         for (int q = 0; q < IS; ++q) {
-            const int idx = threadIdx.x + q * NT;
+            const int idx = tid<OPQ>() + q * NT;
             int uu, k;
             pair_map(idx, uu, k);
             const int p = b * U + uu;
@@ -246,7 +248,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     auto row_unpack_inverse = [&](const SRow (&sv)[IS]) {
 #pragma unroll
         for (int q = 0; q < IS; ++q) {
-            const int idx = threadIdx.x + q * NT;
+            const int idx = tid<OPQ>() + q * NT;
             if (idx >= U * H) continue;
             int uu, k;
             pair_map(idx, uu, k);
@@ -282,7 +284,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         const __amdgpu_buffer_rsrc_t Yr = make_rsrc(Ys, (unsigned)(3 * DD) * 4u);
 #pragma unroll
         for (int q = 0; q < IH; ++q) {
-            const int e = threadIdx.x + q * NT;
+            const int e = tid<OPQ>() + q * NT;
             const int row = e / HC, i = e % HC;
             const int c = row / HR, rr = row - c * HR;
             const int j = 2 * b * U - 1 + rr;
@@ -293,7 +295,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     auto halo_store = [&](const float (&hv)[IH]) {
 #pragma unroll
         for (int q = 0; q < IH; ++q) {
-            const int e = threadIdx.x + q * NT;
+            const int e = tid<OPQ>() + q * NT;
             const int row = e / HC, i = e % HC;
             if (row < 3 * HR) halo[row * HW + 1 + i] = hv[q];
         }
@@ -320,7 +322,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         const bool need_acc = (mode == MODE_RK4 && s > 0) || (mode == MODE_HEUN && s == 1);
 #pragma unroll
         for (int q = 0; q < IC; ++q) {
-            const int idx = threadIdx.x + q * NT;
+            const int idx = tid<OPQ>() + q * NT;
             const int uu = idx / D, i = idx - uu * D;
             const int p = b * U + uu;
             const bool live = idx < U * D && p < d.n_pairs;
@@ -342,7 +344,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     auto cell_update = [&](int b, int s, long long n, float* Yn) {
 #pragma unroll
         for (int q = 0; q < IC; ++q) {
-            const int idx = threadIdx.x + q * NT;
+            const int idx = tid<OPQ>() + q * NT;
             if (idx >= U * D) continue;
             const int uu = idx / D, i = idx - uu * D;
             const int p = b * U + uu;
@@ -513,7 +515,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         const float* Yrec = recd + ((size_t)(ns * 4 + ss) * 2) * 3 * DD;
         const float* Hrec = Yrec + 3 * DD;
         const float* Hfin = recd + ((size_t)(nf * 4 + sf) * 2 + 1) * 3 * DD;
-        for (int idx = threadIdx.x; idx < U * D; idx += NT) {
+        for (int idx = tid<OPQ>(); idx < U * D; idx += NT) {
             const int uu = idx / D, i = idx - uu * D;
             const int p = b * U + uu;
             if (p >= d.n_pairs) continue;
@@ -649,7 +651,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     auto relax_update = [&](int b, const float* cur, float* nxt, double lx, double ly, double Xc, double Yc) {
         const double half = (D - 1) / 2.0;
         const float kap = (float)a.kappa;
-        for (int idx = threadIdx.x; idx < U * D; idx += NT) {
+        for (int idx = tid<OPQ>(); idx < U * D; idx += NT) {
             const int uu = idx / D, i = idx - uu * D;
             const int p = b * U + uu;
             if (p >= d.n_pairs) continue;
@@ -730,8 +732,8 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             red[wv][2] = s2;
         }
         __syncthreads();
-        if (threadIdx.x < 3) {
-            const int q = threadIdx.x;
+        if (tid<OPQ>() < 3) {
+            const int q = tid<OPQ>();
             double acc = 0.0;
             for (int w = 0; w < 3 * UG; ++w) acc += red[w][q];
             d.part[g * PART_STRIDE + q] = acc;
@@ -771,8 +773,8 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                     for (int q = 1; q < 8; ++q) red8[wv][q] = vs[q - 1];
                 }
                 __syncthreads();
-                if (threadIdx.x < 8) {
-                    const int q = threadIdx.x;
+                if (tid<OPQ>() < 8) {
+                    const int q = tid<OPQ>();
                     double acc = 0.0;
                     for (int w = 0; w < 3 * UG; ++w) acc = (q == 0) ? fmax(acc, red8[w][q]) : acc + red8[w][q];
                     st_shd(d.part + g * PART_STRIDE + q, acc);
@@ -803,7 +805,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         // the result lives in cur; bring it back to m
         if (cur != m) {
             for (int b = g; b < n_rb; b += G)
-                for (int idx = threadIdx.x; idx < U * D; idx += NT) {
+                for (int idx = tid<OPQ>(); idx < U * D; idx += NT) {
                     const int uu = idx / D, i = idx - uu * D;
                     const int p = b * U + uu;
                     if (p >= d.n_pairs) continue;
@@ -814,7 +816,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                     }
                 }
         }
-        if (g == 0 && threadIdx.x == 0) {
+        if (g == 0 && tid<OPQ>() == 0) {
             double* o = a.relax_out + 8 * d.k;
             o[0] = lx;
             o[1] = ly;
