@@ -147,11 +147,14 @@ int llg_rk4_step(llg_disk h, float* m, long long nsteps, const llg_params* p, vo
 /* nsteps Heun (H2) steps in place (Sec. III.C): g = b dtau + sigma w,
  * Delta(m) = m x [g - alpha (m x g)], predictor m~ = m + Delta(m), corrector
  * m' = m + (Delta(m) + Delta(m~))/2 with the same w, sigma = sqrt(2 alpha T dtau)
- * (over 1 + alpha^2 when fd_factor is set).  Step s (= step0 + n) of disk k
- * draws w for box cell q = iy*D + ix from Philox4x64-10 with counter
- * (s, q, replica + k, 0) and key (seed, 0); the top 24 bits of the four
- * outputs give uniforms u0..u3 and w = (sqrt(-2 ln u0) cos 2pi u1,
- * sqrt(-2 ln u0) sin 2pi u1, sqrt(-2 ln u2) cos 2pi u3). */
+ * (over 1 + alpha^2 when fd_factor is set).  At step s (= step0 + n) the two
+ * cells (2p, ix) and (2p+1, ix) of row pair p of disk k draw their noise from
+ * one Philox4x64-10 block with counter (s, p*D + ix, replica + k, 0) and key
+ * (seed, 0): its words x0..x2 give the uniforms U = (hi x0, lo x0, hi x1,
+ * lo x1, hi x2, lo x2), hi(x) = ((x >> 40) + 0.5) 2^-24 and
+ * lo(x) = (((x >> 8) mod 2^24) + 0.5) 2^-24, and three Box-Muller pairs
+ * n_2k = sqrt(-2 ln U_2k) cos(2 pi U_2k+1), n_2k+1 = sqrt(-2 ln U_2k) sin(2 pi U_2k+1);
+ * the even row takes w = (n0, n1, n2), the odd row (n3, n4, n5). */
 int llg_heun_step(llg_disk h, float* m, long long nsteps, unsigned long long seed,
                   unsigned long long step0, unsigned int replica, const llg_params* p,
                   void* stream);
