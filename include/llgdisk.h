@@ -159,6 +159,32 @@ int llg_heun_step(llg_disk h, float* m, long long nsteps, unsigned long long see
                   unsigned long long step0, unsigned int replica, const llg_params* p,
                   void* stream);
 
+/* step0 value for llg_heun_step: take the first step index from the handle's
+ * device-side step counter and advance the counter by nsteps afterwards (in
+ * stream order), so that repeated calls, and replays of a graph, continue one
+ * noise stream without host involvement. */
+#define LLG_STEP_COUNTER (~0ull)
+
+/* Set the handle's step counter (enqueued on stream) / read it (host,
+ * synchronises the stream). */
+int llg_step_counter_set(llg_disk h, unsigned long long step, void* stream);
+int llg_step_counter_get(llg_disk h, unsigned long long* step, void* stream);
+
+/* Ragged batches as an executable hipGraph: one graph runs nsteps RK4
+ * (integrator 0) or Heun (integrator 1) steps of every disk of h on the state
+ * m (device, packed like the handle's disks), exactly like llg_rk4_step /
+ * llg_heun_step with step0 = LLG_STEP_COUNTER: a barrier-reset kernel node,
+ * the persistent launch as a cooperative kernel node, and for Heun a node that
+ * advances the step counter.  The graph copies the parameters p (host, one per
+ * disk) at creation and keeps the handle's launch plan of that moment; the
+ * handle must outlive the graph, and replays must not overlap other calls on
+ * the same handle.  Creation synchronises the device. */
+typedef struct llg_graph_s* llg_graph;
+int llg_graph_create(llg_disk h, int integrator, float* m, long long nsteps, const llg_params* p,
+                     unsigned long long seed, unsigned int replica, llg_graph* out);
+int llg_graph_launch(llg_graph g, void* stream);
+void llg_graph_destroy(llg_graph g);
+
 /* Lagrange-constrained alignment relaxation (Sec. IV) in place: every sweep
  * evaluates the full induction b and sets m_i <- (b_i + b^lam_i + kappa m_i)/|.|
  * for all cells at once, with the fictitious field b^lam_i = 2 m_z,i

@@ -19,6 +19,8 @@ class LLGParamsC(ctypes.Structure):
 
 
 # name -> (restype, argtypes)
+STEP_COUNTER = 2**64 - 1      # LLG_STEP_COUNTER
+
 SIGNATURES = {
     "llg_params_from_si": (c_int, [c_double, c_double, c_double, c_double, c_double, c_double, c_double,
                                    c_double, ctypes.POINTER(LLGParamsC), P_double]),
@@ -36,6 +38,12 @@ SIGNATURES = {
     "llg_rhs": (c_int, [c_vp, c_vp, c_vp, ctypes.POINTER(LLGParamsC), c_vp]),
     "llg_rk4_step": (c_int, [c_vp, c_vp, c_ll, ctypes.POINTER(LLGParamsC), c_vp]),
     "llg_heun_step": (c_int, [c_vp, c_vp, c_ll, c_ull, c_ull, c_uint, ctypes.POINTER(LLGParamsC), c_vp]),
+    "llg_step_counter_set": (c_int, [c_vp, c_ull, c_vp]),
+    "llg_step_counter_get": (c_int, [c_vp, ctypes.POINTER(c_ull), c_vp]),
+    "llg_graph_create": (c_int, [c_vp, c_int, c_vp, c_ll, ctypes.POINTER(LLGParamsC), c_ull, c_uint,
+                                 ctypes.POINTER(c_vp)]),
+    "llg_graph_launch": (c_int, [c_vp, c_vp]),
+    "llg_graph_destroy": (None, [c_vp]),
     "llg_relax": (c_int, [c_vp, c_vp, P_double, c_double, c_double, c_ll, ctypes.POINTER(LLGParamsC), c_vp, c_vp]),
     "llg_rk4_record": (c_int, [c_vp, c_vp, c_ll, ctypes.POINTER(LLGParamsC), c_vp, c_vp]),
     "llg_rk4_vjp": (c_int, [c_vp, c_vp, c_ll, c_vp, c_vp, ctypes.POINTER(LLGParamsC), c_vp]),

@@ -175,12 +175,33 @@ class Disk:
         check(_lib.load().llg_rk4_step(self._h, _ptr(m), int(nsteps), self._params(params), _stream()), "llg_rk4_step")
         return m
 
-    def heun_step(self, m: torch.Tensor, nsteps: int, params, *, seed: int, step0: int = 0,
+    def heun_step(self, m: torch.Tensor, nsteps: int, params, *, seed: int, step0=0,
                   replica: int = 0) -> torch.Tensor:
+        """step0=None: continue from the handle's device step counter (and advance it)."""
         m = self._state(m)
-        check(_lib.load().llg_heun_step(self._h, _ptr(m), int(nsteps), int(seed), int(step0), int(replica),
+        s0 = _lib.STEP_COUNTER if step0 is None else int(step0)
+        check(_lib.load().llg_heun_step(self._h, _ptr(m), int(nsteps), int(seed), s0, int(replica),
                                         self._params(params), _stream()), "llg_heun_step")
         return m
+
+    def set_step(self, step: int):
+        check(_lib.load().llg_step_counter_set(self._h, int(step), _stream()), "llg_step_counter_set")
+
+    def get_step(self) -> int:
+        v = ctypes.c_ulonglong(0)
+        check(_lib.load().llg_step_counter_get(self._h, ctypes.byref(v), _stream()), "llg_step_counter_get")
+        return int(v.value)
+
+    def graph(self, integrator: str, m: torch.Tensor, nsteps: int, params, *, seed: int = 0,
+              replica: int = 0) -> "Graph":
+        """An executable hipGraph of nsteps RK4 or Heun steps on m (Heun continues the
+        device step counter on every replay)."""
+        m = self._state(m)
+        g = ctypes.c_void_p()
+        check(_lib.load().llg_graph_create(self._h, {"rk4": 0, "heun": 1}[integrator], _ptr(m), int(nsteps),
+                                           self._params(params), int(seed), int(replica), ctypes.byref(g)),
+              "llg_graph_create")
+        return Graph(g, self, m)
 
     def relax(self, m: torch.Tensor, X_nm, params, *, kappa: float = 2.0, tol: float = 2e-6,
               max_sweeps: int = 100000) -> torch.Tensor:
@@ -256,6 +277,29 @@ class Disk:
 
 
 # ---------------------------------------------------------------- C-ABI-named functions
+class Graph:
+    """Executable graph from Disk.graph; launch() enqueues one replay on the current stream."""
+
+    def __init__(self, handle, disk: Disk, m: torch.Tensor):
+        self._g = handle
+        self._disk = disk      # the handle and the state must outlive the graph
+        self._m = m
+
+    def launch(self):
+        check(_lib.load().llg_graph_launch(self._g, _stream()), "llg_graph_launch")
+
+    def close(self):
+        if self._g:
+            _lib.load().llg_graph_destroy(self._g)
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def build_kernels(R_nm: float, L_nm: float, a_nm: float = 2.0, P: int = 0) -> Disk:
     return Disk.build(R_nm, L_nm, a_nm, P)
 

@@ -11,6 +11,14 @@ __global__ void zero_u32(unsigned int* p, int n) {
     if (i < n) p[i] = 0u;
 }
 
+// The handle's Heun step counter: set, and advance after a launch that used it.
+__global__ void set_u64(unsigned long long* p, unsigned long long v) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *p = v;
+}
+__global__ void advance_u64(unsigned long long* p, unsigned long long n) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *p += n;
+}
+
 // E = E_ex + E_demag + E_ext per disk from the per-workgroup partials, summed in
 // workgroup order (deterministic).
 __global__ void energy_finalize(const DiskDesc* disks, int n, double* out) {

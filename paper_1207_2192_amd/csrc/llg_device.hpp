@@ -67,6 +67,7 @@ struct KArgs {
     float* rec;           // RK4 stage record (stage states and demag fields), may be null
     long long nsteps;
     unsigned long long seed, step0;
+    const unsigned long long* step_ptr;   // if set, the Heun step index is read here instead of step0
     unsigned int replica0;
     int mode;
     int* err;

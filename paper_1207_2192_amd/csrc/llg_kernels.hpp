@@ -94,6 +94,8 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     unsigned int epoch = 0;
     // the field kernel serves demag / rhs / energy at run time; the integrators are compiled per mode
     const int mode = (MODE == MODE_DEMAG) ? a.mode : MODE;
+    // first Heun step index: from the handle's device counter when one is given
+    const unsigned long long step0 = (MODE == MODE_HEUN && a.step_ptr) ? *a.step_ptr : a.step0;
 
     // ---- packed rows of a state into LDS (masked), columns [0, D)
     auto load_state_rows = [&](int b, const float* src) {
@@ -368,7 +370,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             float nxt[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
             float3 wn[2];
             if (mode == MODE_HEUN && (in_disk(j0, i, D) || (j0 + 1 < D && in_disk(j0 + 1, i, D))))
-                thermal_normals_pair(a.seed, a.step0 + (unsigned long long)n, (unsigned long long)(p * D + i),
+                thermal_normals_pair(a.seed, step0 + (unsigned long long)n, (unsigned long long)(p * D + i),
                                      (unsigned long long)(a.replica0 + d.k), wn[0], wn[1]);
 #pragma unroll
             for (int r = 0; r < 2; ++r) {

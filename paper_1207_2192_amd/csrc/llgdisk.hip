@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <numeric>
 #include <string>
 #include <tuple>
@@ -168,6 +169,7 @@ struct llg_disk_s {
     unsigned int* bars = nullptr;
     int n_bars = 0;
     int* err_dev = nullptr;
+    unsigned long long* step_dev = nullptr;   // Heun step counter (LLG_STEP_COUNTER)
     int UG = 1;                       // wavefront groups per workgroup of the persistent launch
     int RSEL = 0;                     // radix policy of the LDS transforms
     int PMAX = 256;                   // largest FFT size of the handle's disks (kernel instance)
@@ -196,6 +198,20 @@ struct llg_disk_s {
             (void)hipFree(p);
             allocs.erase(it);
         }
+    }
+};
+
+// An executable graph of one persistent launch (barrier reset, integrator,
+// step-counter advance) with its own copy of the parameters.
+struct llg_graph_s {
+    llg_disk h = nullptr;
+    DiskPrm* prm = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~llg_graph_s() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (prm) (void)hipFree(prm);
     }
 };
 
@@ -440,6 +456,8 @@ int create(int n, const double* R_nm, const double* L_nm, double a_nm, const int
     if ((rc = h->dalloc(&h->bars, h->n_bars))) return bail(rc);
     if ((rc = h->dalloc(&h->err_dev, 1))) return bail(rc);
     HIP_TRY(hipMemset(h->err_dev, 0, sizeof(int)));
+    if ((rc = h->dalloc(&h->step_dev, 1))) return bail(rc);
+    HIP_TRY(hipMemset(h->step_dev, 0, sizeof(unsigned long long)));
     h->desc.assign(n, DiskDesc{});
     for (int k = 0; k < n; ++k) {
         DiskDesc& d = h->desc[k];
@@ -512,15 +530,13 @@ int upload_params(llg_disk h, const llg_params* p, hipStream_t st) {
     return 0;
 }
 
-int launch(llg_disk h, int mode, float* m, float* out, long long nsteps, unsigned long long seed,
-           unsigned long long step0, unsigned int replica0, hipStream_t st, float* rec = nullptr,
-           const double* relax_x = nullptr, double* relax_out = nullptr, double kappa = 0.0, double tol = 0.0) {
-    const int nb = (h->n_bars + 255) / 256;
-    hipLaunchKernelGGL(zero_u32, dim3(nb), dim3(256), 0, st, h->bars, h->n_bars);
-    HIP_TRY(hipGetLastError());
+KArgs make_args(llg_disk h, const DiskPrm* prm, int mode, float* m, float* out, long long nsteps,
+                unsigned long long seed, unsigned long long step0, unsigned int replica0,
+                const unsigned long long* step_ptr, float* rec, const double* relax_x, double* relax_out,
+                double kappa, double tol) {
     KArgs a;
     a.disks = h->desc_dev;
-    a.prm = h->prm_dev;
+    a.prm = prm;
     a.wg2disk = h->wg2disk;
     a.wg2local = h->wg2local;
     a.m = m;
@@ -533,12 +549,29 @@ int launch(llg_disk h, int mode, float* m, float* out, long long nsteps, unsigne
     a.nsteps = nsteps;
     a.seed = seed;
     a.step0 = step0;
+    a.step_ptr = step_ptr;
     a.replica0 = replica0;
     a.mode = mode;
     a.err = h->err_dev;
+    return a;
+}
+
+int launch(llg_disk h, int mode, float* m, float* out, long long nsteps, unsigned long long seed,
+           unsigned long long step0, unsigned int replica0, hipStream_t st, float* rec = nullptr,
+           const double* relax_x = nullptr, double* relax_out = nullptr, double kappa = 0.0, double tol = 0.0,
+           const unsigned long long* step_ptr = nullptr) {
+    const int nb = (h->n_bars + 255) / 256;
+    hipLaunchKernelGGL(zero_u32, dim3(nb), dim3(256), 0, st, h->bars, h->n_bars);
+    HIP_TRY(hipGetLastError());
+    KArgs a = make_args(h, h->prm_dev, mode, m, out, nsteps, seed, step0, replica0, step_ptr, rec, relax_x,
+                        relax_out, kappa, tol);
     void* args[] = {&a};
-    HIP_TRY(hipLaunchCooperativeKernel(persistent_kernel(mode, h->UG, h->RSEL, h->PMAX), dim3(h->n_wg), dim3(WG_THREADS * h->UG), args, 0,
-                                       st));
+    HIP_TRY(hipLaunchCooperativeKernel(persistent_kernel(mode, h->UG, h->RSEL, h->PMAX), dim3(h->n_wg),
+                                       dim3(WG_THREADS * h->UG), args, 0, st));
+    if (step_ptr) {
+        hipLaunchKernelGGL(advance_u64, dim3(1), dim3(64), 0, st, h->step_dev, (unsigned long long)nsteps);
+        HIP_TRY(hipGetLastError());
+    }
     return 0;
 }
 
@@ -768,8 +801,96 @@ int llg_heun_step(llg_disk h, float* m, long long nsteps, unsigned long long see
     if (nsteps < 0) return fail(LLG_EINVAL, "nsteps < 0");
     if (nsteps == 0) return 0;
     if ((rc = upload_params(h, p, (hipStream_t)stream))) return rc;
+    if (step0 == LLG_STEP_COUNTER)
+        return launch(h, MODE_HEUN, m, nullptr, nsteps, seed, 0, replica, (hipStream_t)stream, nullptr, nullptr,
+                      nullptr, 0.0, 0.0, h->step_dev);
     return launch(h, MODE_HEUN, m, nullptr, nsteps, seed, step0, replica, (hipStream_t)stream);
 }
+
+int llg_step_counter_set(llg_disk h, unsigned long long step, void* stream) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    hipLaunchKernelGGL(set_u64, dim3(1), dim3(64), 0, (hipStream_t)stream, h->step_dev, step);
+    HIP_TRY(hipGetLastError());
+    return 0;
+}
+
+int llg_step_counter_get(llg_disk h, unsigned long long* step, void* stream) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!step) return fail(LLG_EINVAL, "null output");
+    HIP_TRY(hipMemcpyAsync(step, h->step_dev, sizeof(unsigned long long), hipMemcpyDeviceToHost, (hipStream_t)stream));
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    return 0;
+}
+
+int llg_graph_create(llg_disk h, int integrator, float* m, long long nsteps, const llg_params* p,
+                     unsigned long long seed, unsigned int replica, llg_graph* out) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!m || !p || !out) return fail(LLG_EINVAL, "null argument");
+    if (integrator != 0 && integrator != 1) return fail(LLG_EINVAL, "integrator must be 0 (RK4) or 1 (Heun)");
+    if (nsteps < 1) return fail(LLG_EINVAL, "nsteps < 1");
+    *out = nullptr;
+    std::unique_ptr<llg_graph_s> g(new llg_graph_s());
+    g->h = h;
+    // the graph keeps its own copy of the parameters
+    if ((rc = upload_params(h, p, nullptr))) return rc;
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMalloc(&g->prm, h->n * sizeof(DiskPrm)));
+    HIP_TRY(hipMemcpy(g->prm, h->prm_dev, h->n * sizeof(DiskPrm), hipMemcpyDeviceToDevice));
+    HIP_TRY(hipGraphCreate(&g->graph, 0));
+    // node 1: clear the barrier counters (a kernel, not a memset node)
+    int n_bars = h->n_bars;
+    unsigned int* bars = h->bars;
+    void* zargs[] = {&bars, &n_bars};
+    hipKernelNodeParams zp{};
+    zp.func = reinterpret_cast<void*>(zero_u32);
+    zp.gridDim = dim3((h->n_bars + 255) / 256);
+    zp.blockDim = dim3(256);
+    zp.kernelParams = zargs;
+    hipGraphNode_t nz, np, na;
+    HIP_TRY(hipGraphAddKernelNode(&nz, g->graph, nullptr, 0, &zp));
+    // node 2: the persistent cooperative launch
+    const int mode = integrator == 0 ? MODE_RK4 : MODE_HEUN;
+    KArgs a = make_args(h, g->prm, mode, m, nullptr, nsteps, seed, 0, replica, integrator == 1 ? h->step_dev : nullptr,
+                        nullptr, nullptr, nullptr, 0.0, 0.0);
+    void* pargs[] = {&a};
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(persistent_kernel(mode, h->UG, h->RSEL, h->PMAX));
+    kp.gridDim = dim3(h->n_wg);
+    kp.blockDim = dim3(WG_THREADS * h->UG);
+    kp.kernelParams = pargs;
+    HIP_TRY(hipGraphAddKernelNode(&np, g->graph, &nz, 1, &kp));
+    hipKernelNodeAttrValue coop{};
+    coop.cooperative = 1;
+    HIP_TRY(hipGraphKernelNodeSetAttribute(np, hipKernelNodeAttributeCooperative, &coop));
+    // node 3 (Heun): advance the step counter so that the next replay continues the noise stream
+    if (integrator == 1) {
+        unsigned long long* sp = h->step_dev;
+        unsigned long long ns = (unsigned long long)nsteps;
+        void* aargs[] = {&sp, &ns};
+        hipKernelNodeParams ap{};
+        ap.func = reinterpret_cast<void*>(advance_u64);
+        ap.gridDim = dim3(1);
+        ap.blockDim = dim3(64);
+        ap.kernelParams = aargs;
+        HIP_TRY(hipGraphAddKernelNode(&na, g->graph, &np, 1, &ap));
+    }
+    HIP_TRY(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+    *out = g.release();
+    return 0;
+}
+
+int llg_graph_launch(llg_graph g, void* stream) {
+    if (!g) return fail(LLG_EINVAL, "null graph");
+    int rc = check_handle(g->h);
+    if (rc) return rc;
+    HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return 0;
+}
+
+void llg_graph_destroy(llg_graph g) { delete g; }
 
 int llg_noise(llg_disk h, unsigned long long seed, unsigned long long step, unsigned int replica, float* w,
               void* stream) {
