@@ -218,6 +218,27 @@ int llg_rk4_record(llg_disk h, float* m, long long nsteps, const llg_params* p, 
 int llg_rk4_vjp(llg_disk h, const float* rec, long long nsteps, float* ybar, double* pgrad,
                 const llg_params* p, void* stream);
 
+/* Adjoint of the Heun (H2) step with the noise replayed (Sec. III.C; the
+ * reverse mode is this library's, the paper integrates forward only).
+ *
+ * llg_heun_record: nsteps Heun steps in place like llg_heun_step (explicit
+ * step0; renorm allowed) that also store, for every step n and both stages
+ * (the field at m_n and at the predictor m~), the stage state and its demag
+ * field into rec: disk k's block starts at float offset
+ * 4 * nsteps * llg_disk_offset(h, k) and holds [nsteps][2][2][3][D][D].
+ * rec needs 4 * nsteps * llg_state_size(h) floats.
+ *
+ * llg_heun_vjp: reverse pass over the same steps (same seed, step0, replica
+ * and params): on entry ybar holds the cotangent of the state after the last
+ * step, on exit the cotangent of the state before the first step.  pgrad (2
+ * doubles per disk) is incremented by d/d alpha (through the torque and
+ * through sigma(alpha) of the noise) and d/d c of the same scalar; the noise
+ * w itself is regenerated from the counter, not stored. */
+int llg_heun_record(llg_disk h, float* m, long long nsteps, unsigned long long seed, unsigned long long step0,
+                    unsigned int replica, const llg_params* p, float* rec, void* stream);
+int llg_heun_vjp(llg_disk h, const float* rec, long long nsteps, unsigned long long seed, unsigned long long step0,
+                 unsigned int replica, float* ybar, double* pgrad, const llg_params* p, void* stream);
+
 /* Cotangent of the core position: with the plaquette r_v and the cutoff set
  * frozen at `core` (the out array llg_vortex_core_position returned for the
  * same m), adds d(rbar . r_c)/dm to mbar (packed like m).  rbar: 2 doubles per

@@ -49,8 +49,9 @@ class Params:
         sigma_s = sqrt(2 alpha T dtau) (Sec. III.C), optionally over (1+alpha^2)."""
         var = 2.0 * self.alpha * self.temp * self.dtau
         if self.fd_factor:
-            var /= 1.0 + self.alpha ** 2
-        return math.sqrt(var)
+            var = var / (1.0 + self.alpha ** 2)
+        # a tensor alpha keeps the autograd graph (gradients through the noise amplitude)
+        return var.sqrt() if hasattr(var, "sqrt") else math.sqrt(var)
 
 
 def exchange_length(mat: Material) -> float:

@@ -47,6 +47,8 @@ SIGNATURES = {
     "llg_relax": (c_int, [c_vp, c_vp, P_double, c_double, c_double, c_ll, ctypes.POINTER(LLGParamsC), c_vp, c_vp]),
     "llg_rk4_record": (c_int, [c_vp, c_vp, c_ll, ctypes.POINTER(LLGParamsC), c_vp, c_vp]),
     "llg_rk4_vjp": (c_int, [c_vp, c_vp, c_ll, c_vp, c_vp, ctypes.POINTER(LLGParamsC), c_vp]),
+    "llg_heun_record": (c_int, [c_vp, c_vp, c_ll, c_ull, c_ull, c_uint, ctypes.POINTER(LLGParamsC), c_vp, c_vp]),
+    "llg_heun_vjp": (c_int, [c_vp, c_vp, c_ll, c_ull, c_ull, c_uint, c_vp, c_vp, ctypes.POINTER(LLGParamsC), c_vp]),
     "llg_core_position_vjp": (c_int, [c_vp, c_vp, c_double, c_vp, c_vp, c_vp, c_vp]),
     "llg_noise": (c_int, [c_vp, c_ull, c_ull, c_uint, c_vp, c_vp]),
     "llg_energy": (c_int, [c_vp, c_vp, ctypes.POINTER(LLGParamsC), c_vp, c_vp]),

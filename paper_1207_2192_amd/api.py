@@ -233,6 +233,24 @@ class Disk:
                                       self._params(params), _stream()), "llg_rk4_vjp")
         return ybar
 
+    def heun_record(self, m: torch.Tensor, nsteps: int, params, rec: torch.Tensor, *, seed: int, step0: int,
+                    replica: int = 0) -> torch.Tensor:
+        m = self._state(m)
+        if rec.numel() < 4 * nsteps * self.state_size or rec.dtype != torch.float32 or not rec.is_contiguous():
+            raise ValueError("rec needs 4 * nsteps * state_size contiguous float32")
+        check(_lib.load().llg_heun_record(self._h, _ptr(m), int(nsteps), int(seed), int(step0), int(replica),
+                                          self._params(params), _ptr(rec), _stream()), "llg_heun_record")
+        return m
+
+    def heun_vjp(self, rec: torch.Tensor, nsteps: int, ybar: torch.Tensor, pgrad: torch.Tensor, params, *,
+                 seed: int, step0: int, replica: int = 0):
+        ybar = self._state(ybar, "ybar")
+        if pgrad.dtype != torch.float64 or pgrad.numel() != 2 * self.n:
+            raise ValueError("pgrad: 2 float64 per disk")
+        check(_lib.load().llg_heun_vjp(self._h, _ptr(rec), int(nsteps), int(seed), int(step0), int(replica),
+                                       _ptr(ybar), _ptr(pgrad), self._params(params), _stream()), "llg_heun_vjp")
+        return ybar
+
     def core_position_vjp(self, m: torch.Tensor, lambda_ex_nm: float, core: torch.Tensor, rbar: torch.Tensor,
                           mbar: torch.Tensor):
         m = self._state(m)

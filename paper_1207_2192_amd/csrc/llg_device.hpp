@@ -39,6 +39,7 @@ struct DiskDesc {
 // Per-disk parameters (device memory, refreshed when they change).
 struct DiskPrm {
     float alpha, c, hx, hy, hz, dtau, sigma;
+    float dsigma;          // d sigma / d alpha (Heun adjoint)
     int renorm;
     double c_d, hx_d, hy_d, hz_d;
 };
@@ -50,7 +51,8 @@ enum Mode : int {
     MODE_RK4 = 3,
     MODE_HEUN = 4,
     MODE_RK4_VJP = 5,
-    MODE_RELAX = 6
+    MODE_RELAX = 6,
+    MODE_HEUN_VJP = 7
 };
 
 constexpr int PART_STRIDE = 8;  // doubles of per-workgroup partial sums

@@ -48,7 +48,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     constexpr int Tf = P / R;
     constexpr int U = UG * (64 / Tf);          // transforms per component in flight per workgroup
     // the adjoint keeps many values per cell in registers: recompute its index arithmetic
-    constexpr bool OPQ = MODE == MODE_RK4_VJP;
+    constexpr bool OPQ = MODE == MODE_RK4_VJP || MODE == MODE_HEUN_VJP;
     constexpr int NT = WG_THREADS * UG;
     constexpr int H = P / 2 + 1;
     const int D = d.D, Dp = d.Dp, G = d.G;
@@ -313,7 +313,9 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     // loaded into registers before the row spectra, so that all of the
     // iteration's loads share one memory latency.
     const bool need_y0 = (mode == MODE_RK4) || (mode == MODE_HEUN);
-    float* const recd = a.rec ? a.rec + (size_t)a.nsteps * 8 * (size_t)d.m_off : nullptr;
+    // stage record: per step, per stage, (stage state, demag field) of [3][D][D]
+    constexpr int NST = (MODE == MODE_HEUN || MODE == MODE_HEUN_VJP) ? 2 : 4;
+    float* const recd = a.rec ? a.rec + (size_t)a.nsteps * (2 * NST) * (size_t)d.m_off : nullptr;
     // Gathered values of one column of a row pair (registers).
     struct Gath {
         float y0[2][3], ac[2][3];
@@ -451,6 +453,15 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                         }
                     }
                 } else if (in) {  // MODE_HEUN
+                    if (recd) {
+                        float* rs = recd + ((size_t)(n * 2 + s) * 2) * 3 * DD + cell;
+                        rs[0] = mx;
+                        rs[DD] = my;
+                        rs[2 * DD] = mz;
+                        rs[3 * DD] = Hx;
+                        rs[4 * DD] = Hy;
+                        rs[5 * DD] = Hz;
+                    }
                     const float3 w = wn[r];
                     const float sg = pr.sigma;
                     const float gx = bx * dt + sg * w.x, gy = by * dt + sg * w.y, gz = bz * dt + sg * w.z;
@@ -645,6 +656,168 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     };
 
 
+    // ---- adjoint of the Heun (H2) step with the noise replayed
+    // Backward stage k <-> step n = N-1-k/2, forward stage s = 1-k%2 (s = 1: the
+    // corrector's field at the predictor m~, s = 0: the field at m_n).  With the
+    // recorded stage state Y, its demag field H and g = b(Y) dtau + sigma w, the
+    // increment Delta(Y, g) = Y x g - alpha Y x (Y x g) has, for a cotangent c,
+    //   direct part  mdir = g x c - alpha [(Y x g) x c + g x (c x Y)]
+    //   g cotangent  gbar = c x Y - alpha (c x Y) x Y
+    //   Y cotangent  mdir + dtau (exchange(gbar) + c_d K gbar)     (K: demag, symmetric)
+    //   alpha_bar += c . (-Y x (Y x g)) + dsigma/dalpha gbar . w,   c_bar += dtau gbar . (h + H).
+    // Step n: y = m_n + (Delta_1 + Delta_2)/2, m~ = m_n + Delta_1, m_{n+1} = y or y/|y|:
+    //   ybar from m_{n+1}bar (through the normalisation), c_2 = ybar/2,
+    //   m~bar = Y_2 cotangent, c_1 = m~bar + ybar/2, m_n bar = ybar + m~bar + Y_1 cotangent.
+    // acc carries ybar (after s = 1 starts) and ybar + m~bar (after s = 0 starts);
+    // aux carries mdir of the started stage; ya / yb carry gbar for its field.
+    auto heun_vjp_update = [&](int b, long long k, long long K) {
+        const long long N = a.nsteps;
+        const bool fin = k > 0, sta = k < K;
+        const long long nf = fin ? N - 1 - (k - 1) / 2 : 0, ns = sta ? N - 1 - k / 2 : 0;
+        const int sf = fin ? 1 - (int)((k - 1) % 2) : 0, ss = sta ? 1 - (int)(k % 2) : 0;
+        const float* Bf = ((k - 1) & 1) ? d.yb : d.ya;      // gbar of the finishing stage
+        float* Bs = (k & 1) ? d.yb : d.ya;                  // gbar of the starting stage
+        const float* Yrec = recd + ((size_t)(ns * 2 + ss) * 2) * 3 * DD;
+        const float* Hrec = Yrec + 3 * DD;
+        const float* Y0rec = recd + ((size_t)(ns * 2) * 2) * 3 * DD;      // m_ns (stage 1 state)
+        const float* Hfin = recd + ((size_t)(nf * 2 + sf) * 2 + 1) * 3 * DD;
+        const float sg = pr.sigma, dsg = pr.dsigma;
+        for (int idx = tid<OPQ>(); idx < U * D; idx += NT) {
+            const int uu = idx / D, i = idx - uu * D;
+            const int p = b * U + uu;
+            if (p >= d.n_pairs) continue;
+            const int j0 = 2 * p;
+            float3 wn[2] = {make_float3(0.f, 0.f, 0.f), make_float3(0.f, 0.f, 0.f)};
+            if (sta && sg != 0.f && (in_disk(j0, i, D) || (j0 + 1 < D && in_disk(j0 + 1, i, D))))
+                thermal_normals_pair(a.seed, step0 + (unsigned long long)ns, (unsigned long long)(p * D + i),
+                                     (unsigned long long)(a.replica0 + d.k), wn[0], wn[1]);
+            const float2 hz2 = BUF(2, uu)[pad16(i)];
+            float nxt[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int j = j0 + r;
+                if (j >= D) break;
+                const int cell = j * D + i;
+                if (!in_disk(j, i, D)) {
+                    if (sta) {
+                        st_sh(Bs + cell, 0.f);
+                        st_sh(Bs + DD + cell, 0.f);
+                        st_sh(Bs + 2 * DD + cell, 0.f);
+                    }
+                    continue;
+                }
+                const bool okl = i > 0 && in_disk(j, i - 1, D), okr = i + 1 < D && in_disk(j, i + 1, D);
+                const bool oku = j > 0 && in_disk(j - 1, i, D), okd = j + 1 < D && in_disk(j + 1, i, D);
+                // ---- finish the stage whose gbar field is in LDS (Kb) and in Bf (exchange)
+                float fin_tot[3] = {0.f, 0.f, 0.f};
+                if (fin) {
+                    const float2 kxy = BUF(r, uu)[pad16(i)];
+                    const float Kb[3] = {kxy.x, kxy.y, r == 0 ? hz2.x : hz2.y};
+                    const float hh[3] = {hxf, hyf, hzf};
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const int o = c * DD + cell;
+                        const float gc = ld_sh(Bf + o);
+                        const float ex = (oku ? ld_sh(Bf + o - D) : 0.f) + (okd ? ld_sh(Bf + o + D) : 0.f) +
+                                         (okl ? ld_sh(Bf + o - 1) : 0.f) + (okr ? ld_sh(Bf + o + 1) : 0.f);
+                        fin_tot[c] = d.aux[o] + dt * (ex + cf * Kb[c]);
+                        e_dm += (double)dt * (double)gc * ((double)hh[c] + (double)Hfin[o]);
+                    }
+                }
+                float ybar[3] = {0.f, 0.f, 0.f};     // cotangent of y (start of s = 1) or acc (s = 0)
+                if (fin && sf == 0) {                // step nf complete: m_nf bar
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const float v = d.acc[c * DD + cell] + fin_tot[c];
+                        st_sh(m + c * DD + cell, v);
+                        ybar[c] = v;
+                    }
+                }
+                if (!sta) continue;
+                // ---- start stage (ns, ss)
+                float Yv[3], bv[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int o = c * DD + cell;
+                    Yv[c] = Yrec[o];
+                    const float ex = (oku ? Yrec[o - D] : 0.f) + (okd ? Yrec[o + D] : 0.f) +
+                                     (okl ? Yrec[o - 1] : 0.f) + (okr ? Yrec[o + 1] : 0.f);
+                    bv[c] = ex + cf * ((c == 0 ? hxf : c == 1 ? hyf : hzf) + Hrec[o]);
+                }
+                const float w3[3] = {r == 0 ? wn[0].x : wn[1].x, r == 0 ? wn[0].y : wn[1].y,
+                                     r == 0 ? wn[0].z : wn[1].z};
+                const float gx = bv[0] * dt + sg * w3[0], gy = bv[1] * dt + sg * w3[1], gz = bv[2] * dt + sg * w3[2];
+                const float Yx = Yv[0], Yy = Yv[1], Yz = Yv[2];
+                // Y x g and Delta(Y, g)
+                const float px = Yy * gz - Yz * gy, py = Yz * gx - Yx * gz, pz = Yx * gy - Yy * gx;
+                const float tx = Yy * pz - Yz * py, ty = Yz * px - Yx * pz, tz = Yx * py - Yy * px;   // Y x (Y x g)
+                float cx, cy, cz;
+                if (ss == 1) {
+                    float yb[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) yb[c] = (k == 0) ? ld_sh(m + c * DD + cell) : ybar[c];
+                    if (pr.renorm) {
+                        // y = (m_n + m~)/2 + Delta_2/2;  ybar = (I - u u^T) m_{n+1}bar / |y|
+                        float y3[3];
+                        const float D2[3] = {px - al * tx, py - al * ty, pz - al * tz};
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) y3[c] = 0.5f * (Y0rec[c * DD + cell] + Yv[c]) + 0.5f * D2[c];
+                        const float nrm = sqrtf(y3[0] * y3[0] + y3[1] * y3[1] + y3[2] * y3[2]);
+                        const float inv = 1.0f / nrm;
+                        const float ux = y3[0] * inv, uy = y3[1] * inv, uz = y3[2] * inv;
+                        const float pu = yb[0] * ux + yb[1] * uy + yb[2] * uz;
+                        yb[0] = (yb[0] - pu * ux) * inv;
+                        yb[1] = (yb[1] - pu * uy) * inv;
+                        yb[2] = (yb[2] - pu * uz) * inv;
+                    }
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) d.acc[c * DD + cell] = yb[c];
+                    cx = 0.5f * yb[0];
+                    cy = 0.5f * yb[1];
+                    cz = 0.5f * yb[2];
+                } else {
+                    // fin_tot = m~bar; acc holds ybar
+                    float yb[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        yb[c] = d.acc[c * DD + cell];
+                        d.acc[c * DD + cell] = yb[c] + fin_tot[c];
+                    }
+                    cx = fin_tot[0] + 0.5f * yb[0];
+                    cy = fin_tot[1] + 0.5f * yb[1];
+                    cz = fin_tot[2] + 0.5f * yb[2];
+                }
+                // c x Y
+                const float qx = cy * Yz - cz * Yy, qy = cz * Yx - cx * Yz, qz = cx * Yy - cy * Yx;
+                // mdir = g x c - alpha [ (Y x g) x c + g x (c x Y) ]
+                const float m1x = gy * cz - gz * cy, m1y = gz * cx - gx * cz, m1z = gx * cy - gy * cx;
+                const float m2x = py * cz - pz * cy, m2y = pz * cx - px * cz, m2z = px * cy - py * cx;
+                const float m3x = gy * qz - gz * qy, m3y = gz * qx - gx * qz, m3z = gx * qy - gy * qx;
+                d.aux[cell] = m1x - al * (m2x + m3x);
+                d.aux[DD + cell] = m1y - al * (m2y + m3y);
+                d.aux[2 * DD + cell] = m1z - al * (m2z + m3z);
+                // gbar = c x Y - alpha (c x Y) x Y
+                const float bx = qx - al * (qy * Yz - qz * Yy);
+                const float by = qy - al * (qz * Yx - qx * Yz);
+                const float bz = qz - al * (qx * Yy - qy * Yx);
+                st_sh(Bs + cell, bx);
+                st_sh(Bs + DD + cell, by);
+                st_sh(Bs + 2 * DD + cell, bz);
+                e_ex += -((double)cx * tx + (double)cy * ty + (double)cz * tz) +
+                        (double)dsg * ((double)bx * w3[0] + (double)by * w3[1] + (double)bz * w3[2]);
+                nxt[r][0] = bx;
+                nxt[r][1] = by;
+                nxt[r][2] = bz;
+            }
+            if (sta) {
+                BUF(0, uu)[pad16(i)] = make_float2(nxt[0][0], nxt[0][1]);
+                BUF(1, uu)[pad16(i)] = make_float2(nxt[1][0], nxt[1][1]);
+                BUF(2, uu)[pad16(i)] = make_float2(nxt[0][2], nxt[1][2]);
+            }
+        }
+        __syncthreads();
+    };
+
     // ---- constrained alignment relaxation (one sweep per field evaluation)
     // cur -> nxt: m <- (b + b^lam + kappa m)/|...| with b^lam = 2 m_z (lam . (r - X)) z-hat.
     // Thread sums (float64): q[0] = max residual |m x (b + b^lam)| of cur, q[1..2] = C(cur),
@@ -831,12 +1004,15 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         }
         return;
     }
-    else if constexpr (MODE == MODE_RK4_VJP) {
-        const long long K = 4 * a.nsteps;
+    else if constexpr (MODE == MODE_RK4_VJP || MODE == MODE_HEUN_VJP) {
+        const long long K = NST * a.nsteps;
         for (long long k = 0; k <= K; ++k) {
             for (int b = g; b < n_rb; b += G) {
                 if (k > 0) row_inverse(b);
-                vjp_update(b, k, K);
+                if constexpr (MODE == MODE_RK4_VJP)
+                    vjp_update(b, k, K);
+                else
+                    heun_vjp_update(b, k, K);
                 if (k < K) row_forward_store(b);
             }
             if (k == K) break;

@@ -27,6 +27,7 @@ const void* persistent_kernel_field(int UG, int RSEL, int PMAX);
 const void* persistent_kernel_rk4(int UG, int RSEL, int PMAX);
 const void* persistent_kernel_heun(int UG, int RSEL, int PMAX);
 const void* persistent_kernel_vjp(int UG, int RSEL, int PMAX);
+const void* persistent_kernel_heun_vjp(int UG, int RSEL, int PMAX);
 const void* persistent_kernel_relax(int UG, int RSEL, int PMAX);
 }  // namespace llg
 
@@ -222,6 +223,7 @@ const void* persistent_kernel(int mode, int UG, int RSEL, int PMAX) {
         case MODE_RK4: return persistent_kernel_rk4(UG, RSEL, PMAX);
         case MODE_HEUN: return persistent_kernel_heun(UG, RSEL, PMAX);
         case MODE_RK4_VJP: return persistent_kernel_vjp(UG, RSEL, PMAX);
+        case MODE_HEUN_VJP: return persistent_kernel_heun_vjp(UG, RSEL, PMAX);
         case MODE_RELAX: return persistent_kernel_relax(UG, RSEL, PMAX);
         default: return persistent_kernel_field(UG, RSEL, PMAX);
     }
@@ -233,7 +235,7 @@ int max_coresident_workgroups(int UG, int RSEL, int PMAX, int* out) {
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     int per_cu = 1 << 30;
-    for (int mode : {MODE_DEMAG, MODE_RK4, MODE_HEUN, MODE_RK4_VJP, MODE_RELAX}) {
+    for (int mode : {MODE_DEMAG, MODE_RK4, MODE_HEUN, MODE_RK4_VJP, MODE_HEUN_VJP, MODE_RELAX}) {
         const void* k = persistent_kernel(mode, UG, RSEL, PMAX);
         if (!k) return fail(LLG_EUNSUPPORTED, "no kernel instance for this launch shape");
         int b = 0;
@@ -512,8 +514,14 @@ int upload_params(llg_disk h, const llg_params* p, hipStream_t st) {
         d.hz = (float)q.hext[2];
         d.dtau = (float)q.dtau;
         double var = 2.0 * q.alpha * q.temp * q.dtau;
-        if (q.fd_factor) var /= 1.0 + q.alpha * q.alpha;
+        double dvar = 2.0 * q.temp * q.dtau;   // d var / d alpha
+        if (q.fd_factor) {
+            const double s = 1.0 + q.alpha * q.alpha;
+            var /= s;
+            dvar *= (1.0 - q.alpha * q.alpha) / (s * s);
+        }
         d.sigma = (float)std::sqrt(var);
+        d.dsigma = var > 0.0 ? (float)(dvar / (2.0 * std::sqrt(var))) : 0.0f;
         d.renorm = q.renorm ? 1 : 0;
         d.c_d = q.c;
         d.hx_d = q.hext[0];
@@ -760,6 +768,33 @@ int llg_rk4_vjp(llg_disk h, const float* rec, long long nsteps, float* ybar, dou
     hipStream_t st = (hipStream_t)stream;
     if ((rc = upload_params(h, p, st))) return rc;
     if ((rc = launch(h, MODE_RK4_VJP, ybar, nullptr, nsteps, 0, 0, 0, st, const_cast<float*>(rec)))) return rc;
+    hipLaunchKernelGGL(grad_finalize, dim3((h->n + 63) / 64), dim3(64), 0, st, h->desc_dev, h->n, pgrad);
+    HIP_TRY(hipGetLastError());
+    return 0;
+}
+
+int llg_heun_record(llg_disk h, float* m, long long nsteps, unsigned long long seed, unsigned long long step0,
+                    unsigned int replica, const llg_params* p, float* rec, void* stream) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!m || !rec) return fail(LLG_EINVAL, "null array");
+    if (nsteps < 1) return fail(LLG_EINVAL, "nsteps < 1");
+    if (step0 == LLG_STEP_COUNTER) return fail(LLG_EINVAL, "the recorded Heun steps need an explicit step0");
+    if ((rc = upload_params(h, p, (hipStream_t)stream))) return rc;
+    return launch(h, MODE_HEUN, m, nullptr, nsteps, seed, step0, replica, (hipStream_t)stream, rec);
+}
+
+int llg_heun_vjp(llg_disk h, const float* rec, long long nsteps, unsigned long long seed, unsigned long long step0,
+                 unsigned int replica, float* ybar, double* pgrad, const llg_params* p, void* stream) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!rec || !ybar || !pgrad) return fail(LLG_EINVAL, "null array");
+    if (nsteps < 1) return fail(LLG_EINVAL, "nsteps < 1");
+    if (step0 == LLG_STEP_COUNTER) return fail(LLG_EINVAL, "the Heun adjoint needs an explicit step0");
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = upload_params(h, p, st))) return rc;
+    if ((rc = launch(h, MODE_HEUN_VJP, ybar, nullptr, nsteps, seed, step0, replica, st, const_cast<float*>(rec))))
+        return rc;
     hipLaunchKernelGGL(grad_finalize, dim3((h->n + 63) / 64), dim3(64), 0, st, h->desc_dev, h->n, pgrad);
     HIP_TRY(hipGetLastError());
     return 0;

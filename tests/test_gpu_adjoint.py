@@ -9,7 +9,7 @@ import torch
 
 import llg_inputs as li
 import oracle
-from oracle.dynamics import rk4_step as o_rk4
+from oracle.dynamics import heun_step as o_heun, rk4_step as o_rk4
 from oracle.observables import core_centroid, vortex_core_position as o_core
 
 pytestmark = pytest.mark.gpu
@@ -50,6 +50,43 @@ def test_rk4_vjp_matches_oracle(R, L, nsteps):
     assert float((got - gm).abs().max()) <= 1e-5 * float(gm.abs().max())
     assert abs(float(pgrad[0]) - float(ga)) <= 1e-5 * abs(float(ga)) + 1e-6
     assert abs(float(pgrad[1]) - float(gc)) <= 1e-5 * abs(float(gc)) + 1e-6
+
+
+@pytest.mark.parametrize("R,L,nsteps,renorm,fd", [(15.0, 5.0, 4, False, False), (30.0, 10.0, 6, True, False),
+                                                  (41.0, 8.0, 3, True, True)])
+def test_heun_vjp_matches_oracle(R, L, nsteps, renorm, fd):
+    # reverse pass of Heun steps with the noise replayed, against autograd through the oracle
+    from paper_1207_2192_amd import Disk, LLGParams
+    disk = Disk.build(R, L)
+    D = disk.D[0]
+    od = oracle.Disk(R, L)
+    m0 = li.smooth_random_field(D, 6)
+    yb = li.random_unit_field(D, 3)
+    kw = dict(alpha=0.1, c=C_PY, dtau=0.03, temp=0.02, renorm=renorm, fd_factor=fd, hext=(0.01, 0.02, -0.01))
+    p = LLGParams(**kw)
+    seed, step0, rep = 99, 1234, 3
+    m = dev(m0)
+    m32 = m.view(3, D, D).double().cpu()
+    rec = torch.empty(4 * nsteps * disk.state_size, dtype=torch.float32, device="cuda")
+    disk.heun_record(m, nsteps, p, rec, seed=seed, step0=step0, replica=rep)
+    ybar = dev(yb * od.mask.numpy())
+    pgrad = torch.zeros(2, dtype=torch.float64, device="cuda")
+    disk.heun_vjp(rec, nsteps, ybar, pgrad, p, seed=seed, step0=step0, replica=rep)
+    disk.check()
+    mr = m32.clone().requires_grad_(True)
+    a = torch.tensor(0.1, dtype=torch.float64, requires_grad=True)
+    c = torch.tensor(C_PY, dtype=torch.float64, requires_grad=True)
+    okw = dict(kw, alpha=a, c=c)
+    yN = o_heun(mr, od, oracle.Params(**okw), seed=seed, step0=step0, replica=rep, nsteps=nsteps)
+    # the recorded forward is the ordinary Heun step
+    assert float((m.view(3, D, D).double().cpu() - yN.detach()).abs().max()) <= 5e-6
+    L_ = (yN * torch.tensor(yb) * od.mask).sum()
+    gm, ga, gc = torch.autograd.grad(L_, (mr, a, c))
+    gm = od.apply_mask(gm)
+    got = ybar.view(3, D, D).double().cpu()
+    assert float((got - gm).abs().max()) <= 2e-5 * float(gm.abs().max())
+    assert abs(float(pgrad[0]) - float(ga)) <= 2e-5 * abs(float(ga)) + 1e-6
+    assert abs(float(pgrad[1]) - float(gc)) <= 2e-5 * abs(float(gc)) + 1e-6
 
 
 def test_core_position_vjp_matches_oracle():
