@@ -92,6 +92,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default launch plan")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"])
     ap.add_argument("--plain", action="store_true", help="loop over single-disk handles instead of one batch")
+    ap.add_argument("--sample-every", type=int, default=100,
+                    help="steps between observable samples (core position + energy) in the timed region; 0 = none")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -157,11 +159,22 @@ def main():
     if args.plain and disk.n > 1:
         plain = [Disk.build(Rs[k], Ls[k], a) for k in range(disk.n)]
 
-    def run(nsteps):
+    eprm = [LLGParams(c=p.c) for p in prms]
+    lam_nm = a / math.sqrt(C_PY)
+    samples = []
+    kernel_events = []
+
+    def run(nsteps, timed=False):
+        """nsteps of the integrator; in the timed region, observables every --sample-every
+        steps (their kernels are part of the timed work) and events around each launch."""
         launches = 0
         left = nsteps
+        chunk = min(args.chunk, args.sample_every) if (timed and args.sample_every) else args.chunk
         while left > 0:
-            k = min(args.chunk, left)
+            k = min(chunk, left)
+            if timed:
+                ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                ev[0].record(stream)
             if plain is not None:
                 for j, dj in enumerate(plain):
                     mj = m[disk.offsets[j]:disk.offsets[j] + 3 * disk.D[j] ** 2]
@@ -176,11 +189,20 @@ def main():
                 else:
                     disk.heun_step(m, k, prms, seed=20120827, step0=step_counter[0], replica=0)
                 launches += 1
+            if timed:
+                ev[1].record(stream)
+                kernel_events.append(ev)
+                if args.sample_every:
+                    if plain is not None:
+                        for j, dj in enumerate(plain):
+                            mj = m[disk.offsets[j]:disk.offsets[j] + 3 * disk.D[j] ** 2]
+                            samples.append((dj.vortex_core_position(mj, lam_nm), dj.energy(mj, eprm[j:j + 1])))
+                    else:
+                        samples.append((disk.vortex_core_position(m, lam_nm), disk.energy(m, eprm)))
             step_counter[0] += k
             left -= k
         return launches
 
-    eprm = [LLGParams(c=p.c) for p in prms]
     e0 = disk.energy(m, eprm)[:, 0].cpu()
     if args.warmup:
         run(args.warmup)
@@ -192,7 +214,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     start.record(stream)
-    launches = run(args.steps)
+    launches = run(args.steps, timed=True)
     stop.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -213,7 +235,9 @@ def main():
     value = Nc * args.steps / gpu_s
     b_step = sum(bytes_per_stage(disk.D[k], disk.P[k]) for k in range(disk.n)) * stages
     b_launch = b_step * args.steps / launches
-    t_launch = gpu_s / launches
+    # duration of the integrator launches alone (the observables between them excluded)
+    kernel_s = sum(e0.elapsed_time(e1) for e0, e1 in kernel_events) / 1e3
+    t_launch = kernel_s / launches
     achieved = b_launch / t_launch / 1e9
     tr = traffic_record(f"{args.workload}_{integrator}")
     traffic = None if tr is None else tr["bytes_per_step"] * args.steps / launches
@@ -234,7 +258,9 @@ def main():
                    "D": sorted(set(disk.D)), "P": sorted(set(disk.P)), "launches": launches,
                    "path": "plain per-disk loop" if plain is not None else "batched persistent launch",
                    "workgroups": disk.launch_shape()[1], "threads_per_workgroup": disk.launch_shape()[2],
-                   "radix_policy": disk.launch_shape()[3], "autotuned": tuned_us is not None},
+                   "radix_policy": disk.launch_shape()[3], "autotuned": tuned_us is not None,
+                   "observables_every": args.sample_every, "observable_samples": len(samples),
+                   "integrator_share_of_time": kernel_s / gpu_s},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "llg_persistent", "bytes_per_cell_step": b_step / Nc},

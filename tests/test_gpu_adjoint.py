@@ -168,3 +168,55 @@ def test_trajectory_gradient_matches_oracle_and_finite_differences():
           - _oracle_loss(m32, 0.01, C_PY - h, od, n_seg, seg, target, frozen)) / (2 * h)
     assert abs(float(a.grad) - float(fa)) <= 5e-3 * abs(float(fa))
     assert abs(float(c.grad) - float(fc)) <= 5e-3 * abs(float(fc))
+
+
+def test_heun_trajectory_gradient_matches_oracle():
+    # checkpointed Heun trajectory at T > 0 with renormalisation, noise replayed in the backward pass
+    from paper_1207_2192_amd import Disk, LLGParams
+    from paper_1207_2192_amd.adjoint import core_trajectory
+    R, L = 30.0, 10.0
+    disk = Disk.build(R, L)
+    D = disk.D[0]
+    od = oracle.Disk(R, L)
+    n_seg, seg = 3, 10
+    seed, step0, rep = 5, 700, 1
+    m0 = dev(li.vortex_ansatz(D, 2.6, 0.4))
+    kw = dict(alpha=0.05, c=C_PY, dtau=0.03, temp=0.01, renorm=True)
+    base = LLGParams(**kw)
+    target = torch.tensor([[2.0 * math.cos(0.1 * k), 2.0 * math.sin(0.1 * k)] for k in range(n_seg + 1)],
+                          dtype=torch.float64)
+    m0g = m0.clone().requires_grad_(True)
+    a = torch.tensor(0.05, dtype=torch.float64, requires_grad=True)
+    c = torch.tensor(C_PY, dtype=torch.float64, requires_grad=True)
+    rc = core_trajectory(m0g, a, c, disk, base, n_seg, seg, LAM, noise=(seed, step0, rep))
+    loss = ((rc - target.cuda()) ** 2).sum()
+    loss.backward()
+    disk.check()
+
+    def o_step(x, s, alpha=0.05, cc=C_PY):
+        return o_heun(x, od, oracle.Params(**dict(kw, alpha=alpha, c=cc)), seed=seed, step0=step0 + s * seg,
+                      replica=rep, nsteps=seg)
+
+    m32 = m0.view(3, D, D).double().cpu()
+    frozen, mo = [], m32.clone()
+    for s in range(n_seg + 1):
+        if s > 0:
+            mo = o_step(mo, s - 1)
+        frozen.append(o_core(mo, od, LAM))
+    mr = m32.clone().requires_grad_(True)
+    ao = torch.tensor(0.05, dtype=torch.float64, requires_grad=True)
+    co = torch.tensor(C_PY, dtype=torch.float64, requires_grad=True)
+    x, Lo = mr, 0.0
+    for s in range(n_seg + 1):
+        if s > 0:
+            x = o_step(x, s - 1, ao, co)
+        f = frozen[s]
+        rcs = core_centroid(x, od, LAM, f[2], f[3], f[4] >= 1)
+        Lo = Lo + ((rcs - target[s]) ** 2).sum()
+    gm, ga, gc = torch.autograd.grad(Lo, (mr, ao, co))
+    assert abs(float(loss) - float(Lo)) <= 1e-4 * abs(float(Lo))
+    got_m = m0g.grad.view(3, D, D).double().cpu()
+    gm = od.apply_mask(gm)
+    assert float((got_m - gm).abs().max()) <= 2e-3 * float(gm.abs().max())
+    assert abs(float(a.grad) - float(ga)) <= 2e-3 * abs(float(ga))
+    assert abs(float(c.grad) - float(gc)) <= 2e-3 * abs(float(gc))
