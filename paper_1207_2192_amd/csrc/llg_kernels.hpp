@@ -42,13 +42,15 @@ struct RowTile {
     static constexpr int floats = 3 * HR * HW;
 };
 
-template <int P, int R, int UG, int MODE>
+template <int P, int R, int UG, int MODE, bool LARGE>
 __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, const DiskPrm& pr, int g,
                                          float2* lds, float2* ltw, float* halo) {
     constexpr int Tf = P / R;
     constexpr int U = UG * (64 / Tf);          // transforms per component in flight per workgroup
-    // the adjoint keeps many values per cell in registers: recompute its index arithmetic
-    constexpr bool OPQ = MODE == MODE_RK4_VJP || MODE == MODE_HEUN_VJP;
+    // the adjoint keeps many values per cell in registers, and kernels that also carry the
+    // P = 512 tiles (LARGE) run at higher occupancy: recompute their index arithmetic
+    // inside the loop
+    constexpr bool OPQ = MODE == MODE_RK4_VJP || MODE == MODE_HEUN_VJP || LARGE;
     constexpr int NT = WG_THREADS * UG;
     constexpr int H = P / 2 + 1;
     const int D = d.D, Dp = d.Dp, G = d.G;
@@ -1113,11 +1115,11 @@ __global__ __launch_bounds__(WG_THREADS* UG) void llg_persistent(KArgs a) {
     const DiskDesc d = a.disks[di];
     const DiskPrm pr = a.prm[di];
     switch (d.P) {
-        case 64: run_disk<64, Radix<64, RSEL>::value, UG, MODE>(a, d, pr, g, lds, ltw, halo); break;
-        case 128: run_disk<128, Radix<128, RSEL>::value, UG, MODE>(a, d, pr, g, lds, ltw, halo); break;
-        case 256: run_disk<256, Radix<256, RSEL>::value, UG, MODE>(a, d, pr, g, lds, ltw, halo); break;
+        case 64: run_disk<64, Radix<64, RSEL>::value, UG, MODE, (PMAX >= 512)>(a, d, pr, g, lds, ltw, halo); break;
+        case 128: run_disk<128, Radix<128, RSEL>::value, UG, MODE, (PMAX >= 512)>(a, d, pr, g, lds, ltw, halo); break;
+        case 256: run_disk<256, Radix<256, RSEL>::value, UG, MODE, (PMAX >= 512)>(a, d, pr, g, lds, ltw, halo); break;
         case 512:
-            if constexpr (PMAX >= 512) run_disk<512, Radix<512, RSEL>::value, UG, MODE>(a, d, pr, g, lds, ltw, halo);
+            if constexpr (PMAX >= 512) run_disk<512, Radix<512, RSEL>::value, UG, MODE, (PMAX >= 512)>(a, d, pr, g, lds, ltw, halo);
             break;
         default: break;
     }

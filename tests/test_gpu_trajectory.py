@@ -34,9 +34,9 @@ def test_small_disk_trajectory_against_float64():
         mo = o_rk4(mo, od, op, 100)
         g = m.view(3, D, D).double().cpu()
         err_m = max(err_m, float((g - mo).abs().max()))
-        cg = disk.vortex_core_position(m, lam).cpu()[0]
+        cg = [float(v) for v in disk.vortex_core_position(m, lam).cpu()[0]]
         cr = o_core(mo, od, lam)
-        core_gpu.append((float(cg[0]), float(cg[1])))
+        core_gpu.append((cg[0], cg[1]))
         core_ref.append(cr[:2])
         err_rc = max(err_rc, float(np.hypot(cg[0] - cr[0], cg[1] - cr[1])))
     disk.check()
