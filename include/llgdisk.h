@@ -188,15 +188,17 @@ void llg_graph_destroy(llg_graph g);
 /* Lagrange-constrained alignment relaxation (Sec. IV) in place: every sweep
  * evaluates the full induction b and sets m_i <- (b_i + b^lam_i + kappa m_i)/|.|
  * for all cells at once, with the fictitious field b^lam_i = 2 m_z,i
- * (lambda . (r_i - X)) z-hat of the constraint sum_i m_z,i^2 (r_i - X) = 0;
+ * (lambda . (r_i - X)) z-hat of the constraint sum_i m_z,i^2 (r_i - X) = 0
+ * over the disk cells with |r_i - X| < cutoff_nm (cutoff_nm = 0: every disk
+ * cell; 4 lambda_ex matches the core-position definition);
  * after each sweep the two multipliers take one Newton step in float64 on the
  * device (Jacobian of the aligned state at fixed b).  Stops when the largest
  * |m_i x (b_i + b^lam_i)| and |C| drop below tol, or after max_sweeps.
  * X_nm (host, 2 per disk): target vortex positions in nm from the disk centre.
  * out (device, 8 doubles per disk): lambda_x, lambda_y, sweeps, residual,
  * C_x, C_y, 0, 0.  The relaxed state's energy U(X) comes from llg_energy. */
-int llg_relax(llg_disk h, float* m, const double* X_nm, double kappa, double tol, long long max_sweeps,
-              const llg_params* p, double* out, void* stream);
+int llg_relax(llg_disk h, float* m, const double* X_nm, double cutoff_nm, double kappa, double tol,
+              long long max_sweeps, const llg_params* p, double* out, void* stream);
 
 /* Adjoint support (the paper integrates forward only; this is the hand-written
  * reverse mode of its RK4 step, Sec. III.A).

@@ -6,9 +6,12 @@ induction and the sweep is repeated until nothing changes; a fictitious field
 that enters through a Lagrange multiplier holds the vortex at a chosen X.
 
 Readings (the constraint form sits in a reference the paper does not restate):
-* constraint  C(m) = sum_i (m_z,i)^2 (r_i - X) = 0  (two equations: the
-  m_z^2-weighted centroid of the disk sits at X, the smooth part of the
-  core-position definition of Sec. IV);
+* constraint  C(m) = sum_{|r_i - X| < r_cut} (m_z,i)^2 (r_i - X) = 0  (two
+  equations: the m_z^2-weighted centroid of the cells within r_cut of X sits
+  at X — the core-position definition of Sec. IV with its 4 lambda_ex cutoff
+  centred on the target); r_cut = None takes the whole disk, which in large
+  disks lets the constraint be met by out-of-plane tails far from the core
+  instead of by moving the core;
 * stationarity of E - lambda.C gives the fictitious field
   b^lam_i = 2 m_z,i (lambda . (r_i - X)) z-hat added to b_i (b = -dE/dm);
 * sweep: all cells at once, m_i <- (b_i + b^lam_i + kappa m_i) / |...|; the
@@ -40,21 +43,27 @@ from .observables import vortex_core_position
 from .units import Params
 
 
-def constraint_terms(m: torch.Tensor, disk: Disk, X_nm):
-    """(dx, dy) of every cell from X in units of a (zero outside the disk) and C(m)."""
+def constraint_terms(m: torch.Tensor, disk: Disk, X_nm, cutoff_nm=None):
+    """(dx, dy) of every cell from X in units of a (zero outside the disk and
+    outside the cutoff circle around X) and C(m)."""
     a = disk.a_nm
-    M = disk.mask.to(torch.float64)
-    dx = (disk.x - X_nm[0] / a) * M
-    dy = (disk.y - X_nm[1] / a) * M
+    dx = disk.x - X_nm[0] / a
+    dy = disk.y - X_nm[1] / a
+    M = disk.mask
+    if cutoff_nm is not None:
+        M = M & (dx * dx + dy * dy < (cutoff_nm / a) ** 2)
+    M = M.to(torch.float64)
+    dx = dx * M
+    dy = dy * M
     w = m[2] ** 2
     return dx, dy, torch.stack([(w * dx).sum(), (w * dy).sum()])
 
 
 def relax(m0: torch.Tensor, disk: Disk, prm: Params, X_nm, *, kappa: float = 2.0, tol: float = 1e-9,
-          max_sweeps: int = 100000):
+          max_sweeps: int = 100000, cutoff_nm=None):
     """Constrained alignment relaxation from m0.  Returns (m, lambda, sweeps, residual, C)."""
     m = normalise(disk.apply_mask(m0.to(torch.float64)), disk)
-    dx, dy, _ = constraint_terms(m, disk, X_nm)
+    dx, dy, _ = constraint_terms(m, disk, X_nm, cutoff_nm)
     lam = torch.zeros(2, dtype=torch.float64)
     res, C = float("inf"), None
     for it in range(max_sweeps):
@@ -63,15 +72,15 @@ def relax(m0: torch.Tensor, disk: Disk, prm: Params, X_nm, *, kappa: float = 2.0
         bl[2] = 2.0 * m[2] * (lam[0] * dx + lam[1] * dy)
         tot = b + bl
         res = float(torch.linalg.vector_norm(torch.linalg.cross(m, tot, dim=0), dim=0).max())
-        _, _, C = constraint_terms(m, disk, X_nm)
+        _, _, C = constraint_terms(m, disk, X_nm, cutoff_nm)
         if res < tol and float(C.abs().max()) < tol:
             return m, lam, it, res, C
         t = tot + kappa * m
         tn = torch.linalg.vector_norm(t, dim=0)
         tn = torch.where(tn > 0, tn, torch.ones_like(tn))
         mn = disk.apply_mask(t / tn)
-        _, _, Cn = constraint_terms(mn, disk, X_nm)
-        g = 4.0 * mn[2] ** 2 * (1.0 - mn[2] ** 2) / tn * disk.mask.to(torch.float64)
+        _, _, Cn = constraint_terms(mn, disk, X_nm, cutoff_nm)
+        g = 4.0 * mn[2] ** 2 * (1.0 - mn[2] ** 2) / tn
         J = torch.stack([torch.stack([(g * dx * dx).sum(), (g * dx * dy).sum()]),
                          torch.stack([(g * dx * dy).sum(), (g * dy * dy).sum()])])
         if float(torch.linalg.det(J).abs()) > 0:
@@ -94,8 +103,10 @@ def thiele_omega(kt: float, k4: float, r_cells: float, Q: int = 1) -> float:
 
 
 def static_potential(disk: Disk, prm: Params, X_list_nm, make_start, lambda_ex_nm: float, **kw):
-    """Relax at each X (nm, along x) and return (r_c in a, U in J, states)."""
+    """Relax at each X (nm, along x; constraint cutoff 4 lambda_ex unless given)
+    and return (r_c in a, U in J, states)."""
     from .observables import energy
+    kw.setdefault("cutoff_nm", 4.0 * lambda_ex_nm)
     rs, Us, states = [], [], []
     for X in X_list_nm:
         m, lam, it, res, C = relax(make_start(X), disk, prm, (X, 0.0), **kw)

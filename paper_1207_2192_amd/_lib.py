@@ -44,7 +44,8 @@ SIGNATURES = {
                                  ctypes.POINTER(c_vp)]),
     "llg_graph_launch": (c_int, [c_vp, c_vp]),
     "llg_graph_destroy": (None, [c_vp]),
-    "llg_relax": (c_int, [c_vp, c_vp, P_double, c_double, c_double, c_ll, ctypes.POINTER(LLGParamsC), c_vp, c_vp]),
+    "llg_relax": (c_int, [c_vp, c_vp, P_double, c_double, c_double, c_double, c_ll, ctypes.POINTER(LLGParamsC), c_vp,
+                          c_vp]),
     "llg_rk4_record": (c_int, [c_vp, c_vp, c_ll, ctypes.POINTER(LLGParamsC), c_vp, c_vp]),
     "llg_rk4_vjp": (c_int, [c_vp, c_vp, c_ll, c_vp, c_vp, ctypes.POINTER(LLGParamsC), c_vp]),
     "llg_heun_record": (c_int, [c_vp, c_vp, c_ll, c_ull, c_ull, c_uint, ctypes.POINTER(LLGParamsC), c_vp, c_vp]),

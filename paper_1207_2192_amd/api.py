@@ -204,16 +204,17 @@ class Disk:
         return Graph(g, self, m)
 
     def relax(self, m: torch.Tensor, X_nm, params, *, kappa: float = 2.0, tol: float = 2e-6,
-              max_sweeps: int = 100000) -> torch.Tensor:
+              max_sweeps: int = 100000, cutoff_nm: float = 0.0) -> torch.Tensor:
         """Constrained relaxation in place; returns [n, 8] float64 (lambda_x, lambda_y,
-        sweeps, residual, C_x, C_y, 0, 0).  X_nm: one (x, y) per disk."""
+        sweeps, residual, C_x, C_y, 0, 0).  X_nm: one (x, y) per disk.  cutoff_nm:
+        constraint over the cells within this distance of X (0 = the whole disk)."""
         m = self._state(m)
         flat = [float(v) for xy in X_nm for v in xy]
         if len(flat) != 2 * self.n:
             raise ValueError("need one (x, y) target per disk")
         X = (ctypes.c_double * (2 * self.n))(*flat)
         out = torch.zeros(self.n, 8, dtype=torch.float64, device=self.device)
-        check(_lib.load().llg_relax(self._h, _ptr(m), X, float(kappa), float(tol), int(max_sweeps),
+        check(_lib.load().llg_relax(self._h, _ptr(m), X, float(cutoff_nm), float(kappa), float(tol), int(max_sweeps),
                                     self._params(params), _ptr(out), _stream()), "llg_relax")
         return out
 

@@ -77,6 +77,7 @@ struct KArgs {
     const double* relax_x;  // target vortex position per disk (2 doubles, units of a from the centre)
     double* relax_out;      // per disk: lambda_x, lambda_y, sweeps, residual, C_x, C_y, 0, 0
     double kappa, tol;
+    double relax_cut2;      // squared constraint radius around the target (units of a^2); <= 0: whole disk
 };
 
 // ---------------------------------------------------------------- Philox4x64-10

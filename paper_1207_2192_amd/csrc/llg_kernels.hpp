@@ -864,7 +864,8 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                     const float2 hxy = BUF(r, uu)[pad16(i)];
                     const float Hz = r == 0 ? hz2.x : hz2.y;
                     const float mx = col[r + 1][0], my = col[r + 1][1], mz = col[r + 1][2];
-                    const double dx = ((double)i - half) - Xc, dy = ((double)j - half) - Yc;
+                    double dx = ((double)i - half) - Xc, dy = ((double)j - half) - Yc;
+                    if (a.relax_cut2 > 0.0 && !(dx * dx + dy * dy < a.relax_cut2)) dx = dy = 0.0;
                     const float bl = (float)(2.0 * (double)mz * (lx * dx + ly * dy));
                     const float bx = (col[r][0] + col[r + 2][0] + lft[r][0] + rgt[r][0]) + cf * (hxf + hxy.x);
                     const float by = (col[r][1] + col[r + 2][1] + lft[r][1] + rgt[r][1]) + cf * (hyf + hxy.y);

@@ -541,7 +541,7 @@ int upload_params(llg_disk h, const llg_params* p, hipStream_t st) {
 KArgs make_args(llg_disk h, const DiskPrm* prm, int mode, float* m, float* out, long long nsteps,
                 unsigned long long seed, unsigned long long step0, unsigned int replica0,
                 const unsigned long long* step_ptr, float* rec, const double* relax_x, double* relax_out,
-                double kappa, double tol) {
+                double kappa, double tol, double relax_cut2 = 0.0) {
     KArgs a;
     a.disks = h->desc_dev;
     a.prm = prm;
@@ -554,6 +554,7 @@ KArgs make_args(llg_disk h, const DiskPrm* prm, int mode, float* m, float* out, 
     a.relax_out = relax_out;
     a.kappa = kappa;
     a.tol = tol;
+    a.relax_cut2 = relax_cut2;
     a.nsteps = nsteps;
     a.seed = seed;
     a.step0 = step0;
@@ -567,12 +568,12 @@ KArgs make_args(llg_disk h, const DiskPrm* prm, int mode, float* m, float* out, 
 int launch(llg_disk h, int mode, float* m, float* out, long long nsteps, unsigned long long seed,
            unsigned long long step0, unsigned int replica0, hipStream_t st, float* rec = nullptr,
            const double* relax_x = nullptr, double* relax_out = nullptr, double kappa = 0.0, double tol = 0.0,
-           const unsigned long long* step_ptr = nullptr) {
+           const unsigned long long* step_ptr = nullptr, double relax_cut2 = 0.0) {
     const int nb = (h->n_bars + 255) / 256;
     hipLaunchKernelGGL(zero_u32, dim3(nb), dim3(256), 0, st, h->bars, h->n_bars);
     HIP_TRY(hipGetLastError());
     KArgs a = make_args(h, h->prm_dev, mode, m, out, nsteps, seed, step0, replica0, step_ptr, rec, relax_x,
-                        relax_out, kappa, tol);
+                        relax_out, kappa, tol, relax_cut2);
     void* args[] = {&a};
     HIP_TRY(hipLaunchCooperativeKernel(persistent_kernel(mode, h->UG, h->RSEL, h->PMAX), dim3(h->n_wg),
                                        dim3(WG_THREADS * h->UG), args, 0, st));
@@ -812,12 +813,13 @@ int llg_core_position_vjp(llg_disk h, const float* m, double lambda_ex_nm, const
     return 0;
 }
 
-int llg_relax(llg_disk h, float* m, const double* X_nm, double kappa, double tol, long long max_sweeps,
-              const llg_params* p, double* out, void* stream) {
+int llg_relax(llg_disk h, float* m, const double* X_nm, double cutoff_nm, double kappa, double tol,
+              long long max_sweeps, const llg_params* p, double* out, void* stream) {
     int rc = check_handle(h);
     if (rc) return rc;
     if (!m || !X_nm || !out) return fail(LLG_EINVAL, "null array");
     if (!(kappa > 0) || !(tol > 0) || max_sweeps < 1) return fail(LLG_EINVAL, "need kappa > 0, tol > 0, max_sweeps >= 1");
+    if (!(cutoff_nm >= 0)) return fail(LLG_EINVAL, "cutoff must be >= 0 (0 = whole disk)");
     hipStream_t st = (hipStream_t)stream;
     if ((rc = upload_params(h, p, st))) return rc;
     // target positions in units of a from the disk centre, staged like the hints
@@ -825,7 +827,9 @@ int llg_relax(llg_disk h, float* m, const double* X_nm, double kappa, double tol
     for (int k = 0; k < 2 * h->n; ++k) h->hint_pin[k] = X_nm[k] / h->a_nm;
     HIP_TRY(hipMemcpyAsync(h->hint_dev, h->hint_pin, 2 * h->n * sizeof(double), hipMemcpyHostToDevice, st));
     HIP_TRY(hipEventRecord(h->hint_event, st));
-    return launch(h, MODE_RELAX, m, nullptr, max_sweeps, 0, 0, 0, st, nullptr, h->hint_dev, out, kappa, tol);
+    const double rcut = cutoff_nm / h->a_nm;
+    return launch(h, MODE_RELAX, m, nullptr, max_sweeps, 0, 0, 0, st, nullptr, h->hint_dev, out, kappa, tol, nullptr,
+                  rcut * rcut);
 }
 
 int llg_heun_step(llg_disk h, float* m, long long nsteps, unsigned long long seed, unsigned long long step0,

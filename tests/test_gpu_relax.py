@@ -23,8 +23,9 @@ def start(D, X_nm, Y_nm=0.0):
     return li.vortex_ansatz(D, X_nm / 2.0 + 1e-3, Y_nm / 2.0 + 1e-3)
 
 
-@pytest.mark.parametrize("R,L,X", [(20.0, 10.0, 3.0), (30.0, 10.0, 4.0), (31.0, 12.0, -2.5)])
-def test_relax_matches_oracle(R, L, X):
+@pytest.mark.parametrize("R,L,X,cut", [(20.0, 10.0, 3.0, 0.0), (30.0, 10.0, 4.0, 0.0), (31.0, 12.0, -2.5, 0.0),
+                                       (30.0, 10.0, 4.0, 4 * LAM), (41.0, 8.0, 5.0, 4 * LAM)])
+def test_relax_matches_oracle(R, L, X, cut):
     from paper_1207_2192_amd import Disk, LLGParams
     disk = Disk.build(R, L)
     D = disk.D[0]
@@ -32,10 +33,11 @@ def test_relax_matches_oracle(R, L, X):
     m0 = start(D, X)
     m = dev(m0)
     p = LLGParams(c=C_PY)
-    out = disk.relax(m, [(X, 0.0)], p, tol=2e-6).cpu()[0]
+    out = disk.relax(m, [(X, 0.0)], p, tol=2e-6, cutoff_nm=cut).cpu()[0]
     disk.check()
     assert float(out[3]) < 2e-6 and abs(float(out[4])) < 2e-6
-    mo, lam, it, res, C = o_relax(torch.tensor(m0), od, oracle.Params(c=C_PY), (X, 0.0), tol=1e-11)
+    mo, lam, it, res, C = o_relax(torch.tensor(m0), od, oracle.Params(c=C_PY), (X, 0.0), tol=1e-11,
+                                  cutoff_nm=cut if cut > 0 else None)
     got = m.view(3, D, D).double().cpu()
     # a residual tol leaves the soft modes of the relaxed state uncertain by about
     # tol over the smallest stiffness; the energy is second order in that error
