@@ -120,13 +120,21 @@ constexpr int padded_len() { return P + P / 16; }
 // buf is touched only by the lanes of this transform until the closing
 // workgroup barrier, so every lane of the workgroup must call this the same
 // number of times.
-template <int P, int R, bool INV>
+// With KEEP (only when P is a power of R) the last stage is not written back:
+// v[j] then holds X[t + j*(P/R)] and no closing barrier is issued.
+template <int P, int R>
+constexpr bool fft_whole_radix() {
+    return (1 << ((ilog2(P) / ilog2(R)) * ilog2(R))) == P;
+}
+
+template <int P, int R, bool INV, bool KEEP = false>
 __device__ __forceinline__ void fft_run(float2 (&v)[R], float2* buf, const float2* tw, int t) {
     constexpr int Tf = P / R;
     constexpr int LOGR = ilog2(R);
     constexpr int LOGP = ilog2(P);
     constexpr int NFULL = LOGP / LOGR;
     constexpr int REM = 1 << (LOGP - NFULL * LOGR);
+    static_assert(!KEEP || REM == 1, "KEEP needs P = R^k");
     int Ns = 1;
 #pragma unroll
     for (int s = 0; s < NFULL; ++s) {
@@ -140,6 +148,7 @@ __device__ __forceinline__ void fft_run(float2 (&v)[R], float2* buf, const float
             for (int j = 1; j < R; ++j) v[j] = INV ? cmulc(v[j], w[j]) : cmul(v[j], w[j]);
         }
         dftR<R, INV>(v);
+        if (KEEP && s == NFULL - 1) break;
         const int kk = t & (Ns - 1);
         const int base = (t - kk) * R + kk;
         wave_sync();

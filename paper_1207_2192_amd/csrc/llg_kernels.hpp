@@ -47,10 +47,10 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                                          float2* lds, float2* ltw, float* halo) {
     constexpr int Tf = P / R;
     constexpr int U = UG * (64 / Tf);          // transforms per component in flight per workgroup
-    // the adjoint keeps many values per cell in registers, and kernels that also carry the
-    // P = 512 tiles (LARGE) run at higher occupancy: recompute their index arithmetic
-    // inside the loop
-    constexpr bool OPQ = MODE == MODE_RK4_VJP || MODE == MODE_HEUN_VJP || LARGE;
+    // the adjoint keeps many values per cell in registers, the P = 512 kernels (LARGE) run
+    // at higher occupancy, and four-group workgroups carry four tiles at once: recompute
+    // their index arithmetic inside the loop instead of holding it in registers
+    constexpr bool OPQ = MODE == MODE_RK4_VJP || MODE == MODE_HEUN_VJP || LARGE || UG >= 4;
     constexpr int NT = WG_THREADS * UG;
     constexpr int H = P / 2 + 1;
     const int D = d.D, Dp = d.Dp, G = d.G;
@@ -162,10 +162,14 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     };
 
     // ---- column kx: forward FFT along y, kernel multiply, inverse FFT along y
-    constexpr int IM = (U * P + NT - 1) / NT;   // spectral points per thread in the multiply
+    // The multiply is fused into the loads of the inverse transform: each lane
+    // forms its own inputs ky = t + j*Tf from the three forward spectra (x wave:
+    // Kxx mx + Kxy my, y wave: Kxy mx + Kyy my, z wave: Kzz mz), with the kernel
+    // spectra of those points loaded together with the column.
+    constexpr bool KEEP = fft_whole_radix<P, R>();
     struct ColIn {
-        float2 v[R];        // this lane's column values
-        float kq[IM][4];    // kernel spectra at this thread's multiply points
+        float2 v[R];      // this lane's column values
+        float k0[R], k1[R];   // kernel spectra at this lane's points (quarter-plane values)
     };
     auto col_load = [&](int b, ColIn& c) {
         const int kx = b * U + u;
@@ -175,50 +179,54 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             const int i = t + j * Tf;
             c.v[j] = (valid && i < D) ? bld2(Srs, soff(wave, kx, i)) : make_float2(0.f, 0.f);
         }
+        // planes: 0 = xx, 1 = yy, 2 = xy, 3 = zz
+        const int pl0 = wave == 0 ? 0 : wave == 1 ? 2 : 3;
+        const int pl1 = wave == 0 ? 2 : 1;
+        const float* sp0 = d.spec + (size_t)pl0 * H * H + (size_t)(valid ? kx : 0) * H;
+        const float* sp1 = d.spec + (size_t)pl1 * H * H + (size_t)(valid ? kx : 0) * H;
 #pragma unroll
-        for (int q = 0; q < IM; ++q) {
-            const int idx = tid<OPQ>() + q * NT;
-            const int uu = idx / P, ky = idx - uu * P;
-            const int kxx = b * U + uu;
-            const bool ok = idx < U * P && kxx < H;
-            const bool lo = ky <= P / 2;
-            const int kq = lo ? ky : P - ky;
-            const float* sp = d.spec + (size_t)(ok ? kxx : 0) * H + kq;
-            c.kq[q][0] = ok ? sp[0] : 0.f;
-            c.kq[q][1] = ok ? sp[H * H] : 0.f;
-            c.kq[q][2] = ok ? sp[2 * H * H] : 0.f;
-            c.kq[q][3] = ok ? sp[3 * H * H] : 0.f;
+        for (int j = 0; j < R; ++j) {
+            const int ky = t + j * Tf;
+            const int kq = ky <= P / 2 ? ky : P - ky;
+            c.k0[j] = valid ? sp0[kq] : 0.f;
+            c.k1[j] = (valid && wave < 2) ? sp1[kq] : 0.f;
         }
     };
     auto col_compute = [&](int b, ColIn& c) {
         const int kx = b * U + u;
         const bool valid = kx < H;
-        fft_run<P, R, false>(c.v, mybuf, ltw, t);
-#pragma unroll
-        for (int q = 0; q < IM; ++q) {
-            const int idx = tid<OPQ>() + q * NT;
-            if (idx >= U * P) continue;
-            const int uu = idx / P, ky = idx - uu * P;
-            if (b * U + uu >= H) continue;
-            // K_xy is odd in ky: the quarter plane holds ky <= P/2
-            const float Kxx = c.kq[q][0], Kyy = c.kq[q][1], Kzz = c.kq[q][3];
-            const float Kxy = ky <= P / 2 ? c.kq[q][2] : -c.kq[q][2];
-            const float2 mx = BUF(0, uu)[pad16(ky)], my = BUF(1, uu)[pad16(ky)], mz = BUF(2, uu)[pad16(ky)];
-            BUF(0, uu)[pad16(ky)] = make_float2(Kxx * mx.x + Kxy * my.x, Kxx * mx.y + Kxy * my.y);
-            BUF(1, uu)[pad16(ky)] = make_float2(Kxy * mx.x + Kyy * my.x, Kxy * mx.y + Kyy * my.y);
-            BUF(2, uu)[pad16(ky)] = make_float2(Kzz * mz.x, Kzz * mz.y);
-        }
-        __syncthreads();
+        fft_run<P, R, false>(c.v, mybuf, ltw, t);   // ends with a workgroup barrier
         float2 v[R];
 #pragma unroll
-        for (int j = 0; j < R; ++j) v[j] = mybuf[pad16(t + j * Tf)];
-        fft_run<P, R, true>(v, mybuf, ltw, t);
-#pragma unroll
         for (int j = 0; j < R; ++j) {
-            const int i = t + j * Tf;
-            if (valid && i < D) bst2(Srs, soff(wave, kx, i), mybuf[pad16(i)]);
+            const int ky = t + j * Tf;
+            const float sg = ky <= P / 2 ? 1.f : -1.f;   // K_xy is odd in ky
+            const float2 A = BUF(wave == 2 ? 2 : 0, u)[pad16(ky)];
+            if (wave == 2) {
+                v[j] = make_float2(c.k0[j] * A.x, c.k0[j] * A.y);
+            } else {
+                const float2 B = BUF(1, u)[pad16(ky)];
+                const float ka = wave == 0 ? c.k0[j] : sg * c.k0[j];
+                const float kb = wave == 0 ? sg * c.k1[j] : c.k1[j];
+                v[j] = make_float2(ka * A.x + kb * B.x, ka * A.y + kb * B.y);
+            }
         }
-        __syncthreads();
+        __syncthreads();   // every wave has its inputs before the transforms overwrite the spectra
+        if constexpr (KEEP) {
+            fft_run<P, R, true, true>(v, mybuf, ltw, t);   // v[j] = column value at row t + j*Tf
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int i = t + j * Tf;
+                if (valid && i < D) bst2(Srs, soff(wave, kx, i), v[j]);
+            }
+        } else {
+            fft_run<P, R, true>(v, mybuf, ltw, t);
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int i = t + j * Tf;
+                if (valid && i < D) bst2(Srs, soff(wave, kx, i), mybuf[pad16(i)]);
+            }
+        }
     };
     // all columns of this workgroup
     auto column_pass = [&]() {
