@@ -50,7 +50,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     // the adjoint keeps many values per cell in registers, the P = 512 kernels (LARGE) run
     // at higher occupancy, and four-group workgroups carry four tiles at once: recompute
     // their index arithmetic inside the loop instead of holding it in registers
-    constexpr bool OPQ = MODE == MODE_RK4_VJP || MODE == MODE_HEUN_VJP || LARGE || UG >= 4;
+    constexpr bool OPQ = MODE == MODE_RK4_VJP || MODE == MODE_HEUN_VJP || LARGE || UG != 2;
     constexpr int NT = WG_THREADS * UG;
     constexpr int H = P / 2 + 1;
     const int D = d.D, Dp = d.Dp, G = d.G;

@@ -171,6 +171,7 @@ struct llg_disk_s {
     int n_bars = 0;
     int* err_dev = nullptr;
     unsigned long long* step_dev = nullptr;   // Heun step counter (LLG_STEP_COUNTER)
+    unsigned plan_modes = 0;          // modes whose co-residency the current plan was checked for
     int UG = 1;                       // wavefront groups per workgroup of the persistent launch
     int RSEL = 0;                     // radix policy of the LDS transforms
     int PMAX = 256;                   // largest FFT size of the handle's disks (kernel instance)
@@ -229,13 +230,18 @@ const void* persistent_kernel(int mode, int UG, int RSEL, int PMAX) {
     }
 }
 
-// Workgroups of the given shape that every mode's kernel can keep co-resident.
-int max_coresident_workgroups(int UG, int RSEL, int PMAX, int* out) {
+constexpr unsigned ALL_MODES = (1u << MODE_DEMAG) | (1u << MODE_RK4) | (1u << MODE_HEUN) | (1u << MODE_RK4_VJP) |
+                               (1u << MODE_HEUN_VJP) | (1u << MODE_RELAX);
+
+// Workgroups of the given shape that the kernels of every mode in `modes` (bit
+// mask) can keep co-resident.
+int max_coresident_workgroups(int UG, int RSEL, int PMAX, int* out, unsigned modes = ALL_MODES) {
     int dev = 0, ncu = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     int per_cu = 1 << 30;
     for (int mode : {MODE_DEMAG, MODE_RK4, MODE_HEUN, MODE_RK4_VJP, MODE_HEUN_VJP, MODE_RELAX}) {
+        if (!(modes & (1u << mode))) continue;
         const void* k = persistent_kernel(mode, UG, RSEL, PMAX);
         if (!k) return fail(LLG_EUNSUPPORTED, "no kernel instance for this launch shape");
         int b = 0;
@@ -271,12 +277,12 @@ int default_unit_groups(llg_disk) {
 }
 
 // Workgroups per disk and the workgroup-to-disk map of the persistent launch.
-int plan(llg_disk h, int UG, int RSEL, const int* wg_per_disk) {
+int plan(llg_disk h, int UG, int RSEL, const int* wg_per_disk, unsigned modes = ALL_MODES) {
     if (UG != 1 && UG != 2 && UG != 4) return fail(LLG_EINVAL, "unit groups must be 1, 2 or 4");
     if (RSEL != 0 && RSEL != 1) return fail(LLG_EINVAL, "radix policy must be 0 or 1");
     const int n = h->n;
     int cap = 0;
-    int rc = max_coresident_workgroups(UG, RSEL, h->PMAX, &cap);
+    int rc = max_coresident_workgroups(UG, RSEL, h->PMAX, &cap, modes);
     if (rc) return rc;
     std::vector<int> useful(n), G(n);
     std::vector<double> work(n);
@@ -382,6 +388,7 @@ int plan(llg_disk h, int UG, int RSEL, const int* wg_per_disk) {
     h->G = G;
     h->UG = UG;
     h->RSEL = RSEL;
+    h->plan_modes = modes;
     if (!h->desc_dev && (rc = h->dalloc(&h->desc_dev, n))) return rc;
     HIP_TRY(hipMemcpy(h->desc_dev, h->desc.data(), n * sizeof(DiskDesc), hipMemcpyHostToDevice));
     return 0;
@@ -569,6 +576,16 @@ int launch(llg_disk h, int mode, float* m, float* out, long long nsteps, unsigne
            unsigned long long step0, unsigned int replica0, hipStream_t st, float* rec = nullptr,
            const double* relax_x = nullptr, double* relax_out = nullptr, double kappa = 0.0, double tol = 0.0,
            const unsigned long long* step_ptr = nullptr, double relax_cut2 = 0.0) {
+    const int kmode = (mode == MODE_RHS || mode == MODE_ENERGY) ? MODE_DEMAG : mode;   // kernel of the mode
+    if (!(h->plan_modes & (1u << kmode))) {
+        int cap = 0;
+        int rc = max_coresident_workgroups(h->UG, h->RSEL, h->PMAX, &cap, 1u << kmode);
+        if (rc) return rc;
+        if (h->n_wg > cap)
+            return fail(LLG_EUNSUPPORTED, "the launch plan (" + std::to_string(h->n_wg) +
+                                              " workgroups, tuned for the integrator) exceeds what this mode keeps "
+                                              "co-resident (" + std::to_string(cap) + "); re-plan with llg_tune");
+    }
     const int nb = (h->n_bars + 255) / 256;
     hipLaunchKernelGGL(zero_u32, dim3(nb), dim3(256), 0, st, h->bars, h->n_bars);
     HIP_TRY(hipGetLastError());
@@ -690,10 +707,12 @@ int llg_autotune(llg_disk h, const float* m, const llg_params* p, int integrator
     Cand bestc{h->UG, h->RSEL, 1.0};
     std::vector<int> bestG = h->G;
     for (const Cand& c : cands) {
-        if ((rc = plan(h, c.UG, c.RSEL, nullptr))) continue;
+        // the tuned plan must keep the integrator and the field kernel (observables) co-resident
+        const unsigned modes = (1u << mode) | (1u << MODE_DEMAG);
+        if ((rc = plan(h, c.UG, c.RSEL, nullptr, modes))) continue;
         std::vector<int> G = h->G;
         for (int k = 0; k < h->n; ++k) G[k] = std::max(1, (int)std::lround(G[k] * c.scale));
-        if ((rc = plan(h, c.UG, c.RSEL, G.data()))) continue;
+        if ((rc = plan(h, c.UG, c.RSEL, G.data(), modes))) continue;
         float ms = 0.f;
         bool ok = true;
         for (int rep = 0; rep < 2 && ok; ++rep) {
@@ -719,7 +738,7 @@ int llg_autotune(llg_disk h, const float* m, const llg_params* p, int integrator
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipFree(work);
-    if ((rc = plan(h, bestc.UG, bestc.RSEL, bestG.data()))) return rc;
+    if ((rc = plan(h, bestc.UG, bestc.RSEL, bestG.data(), (1u << mode) | (1u << MODE_DEMAG)))) return rc;
     if (best_us) *best_us = best * 1e3 / (double)probe_steps;
     return 0;
 }
