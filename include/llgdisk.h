@@ -149,10 +149,10 @@ int llg_rk4_step(llg_disk h, float* m, long long nsteps, const llg_params* p, vo
  * m' = m + (Delta(m) + Delta(m~))/2 with the same w, sigma = sqrt(2 alpha T dtau)
  * (over 1 + alpha^2 when fd_factor is set).  At step s (= step0 + n) the two
  * cells (2p, ix) and (2p+1, ix) of row pair p of disk k draw their noise from
- * one Philox4x64-10 block with counter (s, p*D + ix, replica + k, 0) and key
- * (seed, 0): its words x0..x2 give the uniforms U = (hi x0, lo x0, hi x1,
- * lo x1, hi x2, lo x2), hi(x) = ((x >> 40) + 0.5) 2^-24 and
- * lo(x) = (((x >> 8) mod 2^24) + 0.5) 2^-24, and three Box-Muller pairs
+ * two Philox4x32-10 blocks with counters (s mod 2^32, s div 2^32, 2q + h,
+ * replica + k), h = 0, 1, q = p*D + ix, and key (seed mod 2^32, seed div 2^32):
+ * every 32-bit output x gives u = ((x >> 8) + 0.5) 2^-24, the uniforms
+ * U0..U5 (block 0, then the first two of block 1) give three Box-Muller pairs
  * n_2k = sqrt(-2 ln U_2k) cos(2 pi U_2k+1), n_2k+1 = sqrt(-2 ln U_2k) sin(2 pi U_2k+1);
  * the even row takes w = (n0, n1, n2), the odd row (n3, n4, n5). */
 int llg_heun_step(llg_disk h, float* m, long long nsteps, unsigned long long seed,

@@ -16,7 +16,7 @@ arithmetic) as single steps, without blocking or fusion:
                     definition) and zero-padded FFT convolution (Sec. II.B).
 * ``dynamics``    - effective induction, LLG right-hand side, RK4, Heun
                     (eq. Bi, damped torque equation, Sec. III.A-C).
-* ``philox``      - Philox4x64-10 counter-based generator + Box-Muller.
+* ``philox``      - Philox4x32-10 counter-based generator + Box-Muller.
 * ``observables`` - energy (eq. Hmm), <m>, vorticity centre and the
                     m_z^2-weighted core position (Sec. IV).
 * ``relax``       - Lagrange-constrained alignment relaxation, k_F fit and

@@ -80,23 +80,23 @@ struct KArgs {
     double relax_cut2;      // squared constraint radius around the target (units of a^2); <= 0: whole disk
 };
 
-// ---------------------------------------------------------------- Philox4x64-10
-// Counter-based generator of Salmon et al. (SC'11): ten rounds of two 64x64->128
+// ---------------------------------------------------------------- Philox4x32-10
+// Counter-based generator of Salmon et al. (SC'11): ten rounds of two 32x32->64
 // multiplies mixed with the other counter words and the key; the key is bumped
 // by two Weyl constants between rounds.
-__device__ __forceinline__ void philox4x64_10(uint64_t& c0, uint64_t& c1, uint64_t& c2, uint64_t& c3,
-                                              uint64_t k0, uint64_t k1) {
-    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
-    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+__device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
+                                              uint32_t k0, uint32_t k1) {
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         if (r > 0) {
             k0 += W0;
             k1 += W1;
         }
-        const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
-        const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
-        const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        const uint32_t hi0 = __umulhi(M0, c0), lo0 = M0 * c0;
+        const uint32_t hi1 = __umulhi(M1, c2), lo1 = M1 * c2;
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
         c1 = lo1;
         c2 = n2;
@@ -104,30 +104,29 @@ __device__ __forceinline__ void philox4x64_10(uint64_t& c0, uint64_t& c1, uint64
     }
 }
 
-// Uniforms in (0, 1) from the top 24 bits and from bits 8..31 of a 64-bit word.
-__device__ __forceinline__ float u24(uint64_t x) {
-    return ((float)(uint32_t)(x >> 40) + 0.5f) * 5.9604644775390625e-08f;  // 2^-24
-}
-__device__ __forceinline__ float u24lo(uint64_t x) {
-    return ((float)(((uint32_t)x) >> 8) + 0.5f) * 5.9604644775390625e-08f;
-}
+// Uniform in (0, 1) from the top 24 bits of a 32-bit word.
+__device__ __forceinline__ float u24(uint32_t x) { return ((float)(x >> 8) + 0.5f) * 5.9604644775390625e-08f; }
 
 // Six standard normals for the two cells (2p, ix), (2p+1, ix) of row pair p:
-// block counter (step, p*D + ix, replica, 0), key (seed, 0); the three words
-// x0..x2 give the uniforms (hi x0, lo x0, hi x1, lo x1, hi x2, lo x2) and three
-// Box-Muller pairs; the even row takes normals 0..2, the odd row 3..5.
+// two blocks with counters (s_lo, s_hi, 2q + h, replica), h = 0, 1, q = p*D + ix,
+// key (seed_lo, seed_hi); the uniforms of block 0 and the first two of block 1
+// give three Box-Muller pairs; the even row takes normals 0..2, the odd row 3..5.
 __device__ __forceinline__ void thermal_normals_pair(unsigned long long seed, unsigned long long step,
                                                      unsigned long long q, unsigned long long replica,
                                                      float3& even, float3& odd) {
-    uint64_t c0 = step, c1 = q, c2 = replica, c3 = 0;
-    philox4x64_10(c0, c1, c2, c3, seed, 0ull);
-    const float ra = sqrtf(-2.0f * logf(u24(c0)));
-    const float rb = sqrtf(-2.0f * logf(u24(c1)));
-    const float rc = sqrtf(-2.0f * logf(u24(c2)));
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const uint32_t s0 = (uint32_t)step, s1 = (uint32_t)(step >> 32), rep = (uint32_t)replica;
+    uint32_t a0 = s0, a1 = s1, a2 = (uint32_t)(2 * q), a3 = rep;
+    philox4x32_10(a0, a1, a2, a3, k0, k1);
+    uint32_t b0 = s0, b1 = s1, b2 = (uint32_t)(2 * q + 1), b3 = rep;
+    philox4x32_10(b0, b1, b2, b3, k0, k1);
+    const float ra = sqrtf(-2.0f * logf(u24(a0)));
+    const float rb = sqrtf(-2.0f * logf(u24(a2)));
+    const float rc = sqrtf(-2.0f * logf(u24(b0)));
     float sa, ca, sb, cb, sc, cc;
-    sincospif(2.0f * u24lo(c0), &sa, &ca);
-    sincospif(2.0f * u24lo(c1), &sb, &cb);
-    sincospif(2.0f * u24lo(c2), &sc, &cc);
+    sincospif(2.0f * u24(a1), &sa, &ca);
+    sincospif(2.0f * u24(a3), &sb, &cb);
+    sincospif(2.0f * u24(b1), &sc, &cc);
     even = make_float3(ra * ca, ra * sa, rb * cb);
     odd = make_float3(rb * sb, rc * cc, rc * sc);
 }

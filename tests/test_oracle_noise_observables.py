@@ -1,5 +1,6 @@
-"""Oracle pins: Philox4x64-10 against numpy's Philox bit generator, the
-Box-Muller normals, energy decompositions and the vortex core position (Sec. IV)."""
+"""Oracle pins: Philox4x32-10 against the known-answer vectors published with
+the Random123 library, the Box-Muller normals, energy decompositions and the
+vortex core position (Sec. IV)."""
 import math
 
 import numpy as np
@@ -11,35 +12,31 @@ import llg_inputs as li
 from oracle import Disk, Params
 from oracle.observables import (energy, energy_from_exchange_field, mean_m, plaquette_windings,
                                 vortex_core_position)
-from oracle.philox import gaussian_field, philox4x64_10, uniforms24, uniforms24_low
+from oracle.philox import gaussian_field, philox4x32_10, uniforms24
 
 C_PY = 0.14298555
 LAM_NM = 5.28906
 
 
-@pytest.mark.parametrize("ctr,key", [((0, 0, 0, 0), (0, 0)), ((5, 0, 0, 0), (7, 9)),
-                                     ((123456789, 2**63 + 11, 3, 2**64 - 1), (2**64 - 7, 99))])
-def test_philox_matches_numpy_bit_generator(ctr, key):
-    # numpy's Philox (4x64, 10 rounds) increments the 256-bit counter before
-    # producing each block of four outputs.
-    bg = np.random.Philox(counter=np.array(ctr, dtype=np.uint64), key=np.array(key, dtype=np.uint64))
-    want = bg.random_raw(8)
-    for blk in range(2):
-        c = (ctr[0] + 1 + blk) % 2**64
-        carry = (ctr[0] + 1 + blk) >> 64
-        got = philox4x64_10((np.uint64(c), np.uint64((ctr[1] + carry) % 2**64), np.uint64(ctr[2]),
-                             np.uint64(ctr[3])), (np.uint64(key[0]), np.uint64(key[1])))
-        assert [int(g) for g in got] == [int(w) for w in want[4 * blk:4 * blk + 4]]
+@pytest.mark.parametrize("ctr,key,want", [
+    ((0, 0, 0, 0), (0, 0), (0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8)),
+    ((0xffffffff,) * 4, (0xffffffff,) * 2, (0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd)),
+    ((0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344), (0xa4093822, 0x299f31d0),
+     (0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1)),
+])
+def test_philox_known_answers(ctr, key, want):
+    # the philox4x32 (10 rounds) known-answer vectors of the Random123 distribution
+    got = philox4x32_10([np.uint64(c) for c in ctr], [np.uint64(k) for k in key])
+    assert [int(g) for g in got] == list(want)
 
 
 def test_uniforms_exact_and_open():
-    x = np.array([0, 2**64 - 1, 2**40, 2**63], dtype=np.uint64)
+    x = np.array([0, 2**32 - 1, 2**8, 2**31, 0xFF], dtype=np.uint64)
     u = uniforms24(x)
     assert u[0] == 0.5 * 2**-24 and u[1] == 1 - 0.5 * 2**-24 and 0 < u.min() and u.max() < 1
-    assert np.all(u * 2**25 == np.round(u * 2**25))   # multiples of 2^-25: exact in FP32
-    v = uniforms24_low(np.array([0, 2**64 - 1, 0xFF, 0x1_0000_0100, 2**32 - 256], dtype=np.uint64))
-    assert v[0] == 0.5 * 2**-24 and v[1] == 1 - 0.5 * 2**-24 and v[2] == v[0]      # bits 0..7 are dropped
-    assert v[3] == 1.5 * 2**-24 and v[4] == v[1]                                   # bit 8 is the lowest kept
+    assert u[2] == 1.5 * 2**-24 and u[4] == u[0]          # bit 8 is the lowest kept
+    assert u[3] == 0.5 + 0.5 * 2**-24
+    assert np.all(u * 2**25 == np.round(u * 2**25))       # multiples of 2^-25: exact in FP32
 
 
 def test_normals_are_standard_and_independent():
