@@ -1014,8 +1014,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             o[7] = 0.0;
         }
         return;
-    }
-    else if constexpr (MODE == MODE_RK4_VJP || MODE == MODE_HEUN_VJP) {
+    } else if constexpr (MODE == MODE_RK4_VJP || MODE == MODE_HEUN_VJP) {
         const long long K = NST * a.nsteps;
         for (long long k = 0; k <= K; ++k) {
             for (int b = g; b < n_rb; b += G) {
@@ -1033,59 +1032,56 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         }
         write_partials(e_ex, e_dm, 0.0);
         return;
-    }
-
-    else {
-    for (int b = g; b < n_rb; b += G) {
-        load_state_rows(b, m);
-        row_forward_store(b);
-    }
-    if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
-
-    // one row iteration of a field evaluation: issue every load, then stage, transform and update
-    auto row_step = [&](int b, int s, long long n, const float* Ys, float* Yn) {
-        float hv[IH];
-        SRow sv[IS];
-        halo_load(b, Ys, hv);
-        gather(b, s);
-        row_load(b, sv);
-        halo_store(hv);
-        row_unpack_inverse(sv);
-        cell_update(b, s, n, Yn);
-    };
-
-    if constexpr (MODE == MODE_DEMAG) {
-        column_pass();
+    } else {
+        // field evaluation and integrators: the row spectra of the input state first
+        for (int b = g; b < n_rb; b += G) {
+            load_state_rows(b, m);
+            row_forward_store(b);
+        }
         if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
-        for (int b = g; b < n_rb; b += G) row_step(b, 0, 0, m, nullptr);
-        if (mode == MODE_ENERGY) write_partials(e_ex, e_dm, e_ext);
-        return;
-    }
 
-    else {
-    constexpr int nst = (MODE == MODE_RK4) ? 4 : 2;
-    for (long long n = 0; n < a.nsteps; ++n) {
-        for (int s = 0; s < nst; ++s) {
+        // one row iteration of a field evaluation: issue every load, then stage, transform and update
+        auto row_step = [&](int b, int s, long long n, const float* Ys, float* Yn) {
+            float hv[IH];
+            SRow sv[IS];
+            halo_load(b, Ys, hv);
+            gather(b, s);
+            row_load(b, sv);
+            halo_store(hv);
+            row_unpack_inverse(sv);
+            cell_update(b, s, n, Yn);
+        };
+
+        if constexpr (MODE == MODE_DEMAG) {
             column_pass();
             if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
-            const bool last = (n == a.nsteps - 1) && (s == nst - 1);
-            const float* Ys;
-            float* Yn;
-            if (nst == 4) {
-                Ys = (s == 0) ? m : (s == 2) ? d.yb : d.ya;
-                Yn = (s == 3) ? m : (s == 1) ? d.yb : d.ya;
-            } else {
-                Ys = (s == 0) ? m : d.ya;
-                Yn = (s == 0) ? d.ya : m;
+            for (int b = g; b < n_rb; b += G) row_step(b, 0, 0, m, nullptr);
+            if (mode == MODE_ENERGY) write_partials(e_ex, e_dm, e_ext);
+        } else {
+            constexpr int nst = (MODE == MODE_RK4) ? 4 : 2;
+            for (long long n = 0; n < a.nsteps; ++n) {
+                for (int s = 0; s < nst; ++s) {
+                    column_pass();
+                    if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
+                    const bool last = (n == a.nsteps - 1) && (s == nst - 1);
+                    // state whose field is evaluated (Ys) and where the next stage state goes (Yn)
+                    const float* Ys;
+                    float* Yn;
+                    if (nst == 4) {
+                        Ys = (s == 0) ? m : (s == 2) ? d.yb : d.ya;
+                        Yn = (s == 3) ? m : (s == 1) ? d.yb : d.ya;
+                    } else {
+                        Ys = (s == 0) ? m : d.ya;
+                        Yn = (s == 0) ? d.ya : m;
+                    }
+                    for (int b = g; b < n_rb; b += G) {
+                        row_step(b, s, n, Ys, Yn);
+                        if (!last) row_forward_store(b);
+                    }
+                    if (!last && !group_barrier(d.bar, ++epoch * G, G, a.err)) return;
+                }
             }
-            for (int b = g; b < n_rb; b += G) {
-                row_step(b, s, n, Ys, Yn);
-                if (!last) row_forward_store(b);
-            }
-            if (!last && !group_barrier(d.bar, ++epoch * G, G, a.err)) return;
         }
-    }
-    }
     }
 #undef BUF
 }
