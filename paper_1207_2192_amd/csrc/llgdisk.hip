@@ -277,32 +277,66 @@ int default_unit_groups(llg_disk) {
 }
 
 // Workgroups per disk and the workgroup-to-disk map of the persistent launch.
-int plan(llg_disk h, int UG, int RSEL, const int* wg_per_disk, unsigned modes = ALL_MODES) {
+//
+// Without explicit counts the plan minimises the slowest disk's estimated
+// stage time within a budget of scale x the co-resident workgroups: disk k on
+// G workgroups takes ceil(ncb/G) column and ceil(nrb/G) row iterations of cost
+// U P log2 P each plus, for G > 1, two group barriers (2500 in the same units:
+// the measured ratio of a barrier to a single-transform P = 256 column
+// iteration); the smallest target T whose per-disk counts (the fewest
+// workgroups that meet T) fit the budget is found by bisection.
+int plan(llg_disk h, int UG, int RSEL, const int* wg_per_disk, unsigned modes = ALL_MODES, double scale = 1.0) {
     if (UG != 1 && UG != 2 && UG != 4) return fail(LLG_EINVAL, "unit groups must be 1, 2 or 4");
     if (RSEL != 0 && RSEL != 1) return fail(LLG_EINVAL, "radix policy must be 0 or 1");
     const int n = h->n;
     int cap = 0;
     int rc = max_coresident_workgroups(UG, RSEL, h->PMAX, &cap, modes);
     if (rc) return rc;
-    std::vector<int> useful(n), G(n);
-    std::vector<double> work(n);
+    std::vector<int> useful(n), G(n), ncb(n), nrb(n);
+    std::vector<double> work(n), iter(n);
     for (int k = 0; k < n; ++k) {
         const int P = h->P[k], D = h->D[k];
         const int U = units_per_wg(P, UG, RSEL);
         const int H = P / 2 + 1;
         const int n_pairs = (D + 1) / 2;
-        useful[k] = std::max((n_pairs + U - 1) / U, (H + U - 1) / U);
+        ncb[k] = (H + U - 1) / U;
+        nrb[k] = (n_pairs + U - 1) / U;
+        useful[k] = std::max(ncb[k], nrb[k]);
         work[k] = (double)(n_pairs + H) * P * std::log2((double)P);
+        iter[k] = (double)U * P * std::log2((double)P);
     }
+    auto stage_time = [&](int k, int g) {
+        return ((ncb[k] + g - 1) / g + (nrb[k] + g - 1) / g) * iter[k] + (g > 1 ? 5000.0 : 0.0);
+    };
+    // fewest workgroups for disk k that meet the target T (or all useful ones)
+    auto g_for = [&](int k, double T) {
+        int g = 1;
+        while (g < useful[k] && stage_time(k, g) > T) ++g;
+        return g;
+    };
     if (wg_per_disk) {
         for (int k = 0; k < n; ++k) {
             if (wg_per_disk[k] < 1) return fail(LLG_EINVAL, "wg_per_disk must be >= 1");
             G[k] = std::min(wg_per_disk[k], useful[k]);
         }
     } else {
-        const double wsum = std::accumulate(work.begin(), work.end(), 0.0);
-        for (int k = 0; k < n; ++k)
-            G[k] = std::max(1, std::min(useful[k], (int)std::floor(cap * work[k] / wsum)));
+        if (!(scale > 0.0 && scale <= 1.0)) return fail(LLG_EINVAL, "plan scale must be in (0, 1]");
+        const long long budget = std::max<long long>(n, (long long)std::floor(cap * scale));
+        double lo = 0.0, hi = 0.0;
+        for (int k = 0; k < n; ++k) hi = std::max(hi, stage_time(k, 1));
+        auto total = [&](double T) {
+            long long t = 0;
+            for (int k = 0; k < n; ++k) t += g_for(k, T);
+            return t;
+        };
+        for (int it = 0; it < 60; ++it) {   // smallest T whose counts fit the budget
+            const double mid = 0.5 * (lo + hi);
+            if (total(mid) <= budget)
+                hi = mid;
+            else
+                lo = mid;
+        }
+        for (int k = 0; k < n; ++k) G[k] = g_for(k, hi);
     }
     long long total = std::accumulate(G.begin(), G.end(), 0LL);
     while (total > cap) {  // trim the disks with the most workgroups
@@ -705,14 +739,10 @@ int llg_autotune(llg_disk h, const float* m, const llg_params* p, int integrator
             for (double sc : {1.0, 0.5, 0.25}) cands.push_back({ug, rs, sc});
     double best = 1e300;
     Cand bestc{h->UG, h->RSEL, 1.0};
-    std::vector<int> bestG = h->G;
     for (const Cand& c : cands) {
         // the tuned plan must keep the integrator and the field kernel (observables) co-resident
         const unsigned modes = (1u << mode) | (1u << MODE_DEMAG);
-        if ((rc = plan(h, c.UG, c.RSEL, nullptr, modes))) continue;
-        std::vector<int> G = h->G;
-        for (int k = 0; k < h->n; ++k) G[k] = std::max(1, (int)std::lround(G[k] * c.scale));
-        if ((rc = plan(h, c.UG, c.RSEL, G.data(), modes))) continue;
+        if ((rc = plan(h, c.UG, c.RSEL, nullptr, modes, c.scale))) continue;
         float ms = 0.f;
         bool ok = true;
         for (int rep = 0; rep < 2 && ok; ++rep) {
@@ -732,13 +762,12 @@ int llg_autotune(llg_disk h, const float* m, const llg_params* p, int integrator
         if (ok && ms > 0 && ms < best) {
             best = ms;
             bestc = c;
-            bestG = h->G;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipFree(work);
-    if ((rc = plan(h, bestc.UG, bestc.RSEL, bestG.data(), (1u << mode) | (1u << MODE_DEMAG)))) return rc;
+    if ((rc = plan(h, bestc.UG, bestc.RSEL, nullptr, (1u << mode) | (1u << MODE_DEMAG), bestc.scale))) return rc;
     if (best_us) *best_us = best * 1e3 / (double)probe_steps;
     return 0;
 }
