@@ -140,31 +140,52 @@ __device__ __forceinline__ void thermal_normals_pair(unsigned long long seed, un
 // the barrier only has to drain the stores (s_waitcnt vmcnt(0)) before it
 // signals arrival.  Read-only data (kernel spectra, masks, twiddles) keeps the
 // normal cached path.
+//
+// Every such pointer refers to global memory; accesses go through it as a
+// global-address-space pointer (gbl), so that they compile to global rather
+// than flat instructions.  (A pending flat access makes the compiler wait for
+// every outstanding memory operation at the next use of any loaded value,
+// which would serialise prefetched loads.)
+#define GLOBAL_AS __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ GLOBAL_AS T* gbl(T* p) {
+    return (GLOBAL_AS T*)p;
+}
 __device__ __forceinline__ float ld_sh(const float* p) {
-    return __uint_as_float(__hip_atomic_load(reinterpret_cast<const unsigned int*>(p), __ATOMIC_RELAXED,
+    return __uint_as_float(__hip_atomic_load(gbl(reinterpret_cast<const unsigned int*>(p)), __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT));
 }
 __device__ __forceinline__ void st_sh(float* p, float v) {
-    __hip_atomic_store(reinterpret_cast<unsigned int*>(p), __float_as_uint(v), __ATOMIC_RELAXED,
+    __hip_atomic_store(gbl(reinterpret_cast<unsigned int*>(p)), __float_as_uint(v), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ float2 ld_sh2(const float2* p) {
-    const unsigned long long u = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long u = __hip_atomic_load(gbl(reinterpret_cast<const unsigned long long*>(p)),
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return make_float2(__uint_as_float((unsigned int)u), __uint_as_float((unsigned int)(u >> 32)));
 }
 __device__ __forceinline__ void st_sh2(float2* p, float2 v) {
     const unsigned long long u =
         (unsigned long long)__float_as_uint(v.x) | ((unsigned long long)__float_as_uint(v.y) << 32);
-    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(gbl(reinterpret_cast<unsigned long long*>(p)), u, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ double ld_shd(const double* p) {
-    return __longlong_as_double((long long)__hip_atomic_load(reinterpret_cast<const unsigned long long*>(p),
+    return __longlong_as_double((long long)__hip_atomic_load(gbl(reinterpret_cast<const unsigned long long*>(p)),
                                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 }
 __device__ __forceinline__ void st_shd(double* p, double v) {
-    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v),
+    __hip_atomic_store(gbl(reinterpret_cast<unsigned long long*>(p)), (unsigned long long)__double_as_longlong(v),
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// read-only float2 through a global pointer
+__device__ __forceinline__ float2 ldg2(const float2* p) {
+    const unsigned long long u = *gbl(reinterpret_cast<const unsigned long long*>(p));
+    return make_float2(__uint_as_float((unsigned int)u), __uint_as_float((unsigned int)(u >> 32)));
+}
+// raise an error flag of the launch
+__device__ __forceinline__ void raise_err(int* err, int code) {
+    __hip_atomic_fetch_or(gbl(err), code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ float4 ld_sh4(const float2* p) {
     const float2 a = ld_sh2(p), b = ld_sh2(p + 1);
@@ -185,6 +206,15 @@ constexpr int CP_DEVICE = 16;   // cache policy: sc1
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, unsigned int bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
 }
+// An offset past the range of every buffer resource: a load there reads 0 and a
+// store is dropped, without a memory access.  Loads guarded this way instead of
+// by a branch are always issued, so the wait before the first use of a value
+// counts only the accesses issued after it and prefetched data stays in flight.
+constexpr int OOB = (int)0x80000000u;
+// read-only data through the normal cached path (kernel spectra, own accumulator)
+__device__ __forceinline__ float bld1c(__amdgpu_buffer_rsrc_t r, int off) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
 __device__ __forceinline__ float bld1(__amdgpu_buffer_rsrc_t r, int off) {
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, CP_DEVICE));
 }
@@ -201,8 +231,13 @@ __device__ __forceinline__ void bst4(__amdgpu_buffer_rsrc_t r, int off, float4 v
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, off, 0, CP_DEVICE);
 }
 
-// Wait until every store this wave issued has completed.
-__device__ __forceinline__ void drain_stores() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+// Wait until every store this wave issued has completed (s_waitcnt vmcnt(0):
+// vmcnt 0, expcnt 7, lgkmcnt 15 in the gfx9 encoding), as an instruction the
+// compiler sees, so that its own wait bookkeeping starts afresh after it.
+__device__ __forceinline__ void drain_stores() {
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+}
 
 // The thread index, optionally passed through an empty asm statement: index
 // arithmetic derived from it is then recomputed where it is used inside the
@@ -229,14 +264,14 @@ __device__ __forceinline__ bool group_barrier(unsigned int* bar, unsigned int ta
     if (G == 1) return true;
     __shared__ int s_ok;
     if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(gbl(bar), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         unsigned int spins = 0;
         int ok = 1;
-        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(gbl(bar), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(1);
             if (++spins > SPIN_LIMIT) {
                 ok = 0;
-                __hip_atomic_fetch_or(err, (int)ERR_BARRIER, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                raise_err(err, (int)ERR_BARRIER);
                 break;
             }
         }

@@ -70,7 +70,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
 #define BUF(w, uu) (lds + ((w) * U + (uu)) * PSK)
     constexpr int HR = RowTile<P, R, UG>::HR, HW = RowTile<P, R, UG>::HW;
 
-    for (int i = tid<OPQ>(); i < P; i += NT) ltw[i] = d.tw[i];
+    for (int i = tid<OPQ>(); i < P; i += NT) ltw[i] = ldg2(d.tw + i);
     for (int r = tid<OPQ>(); r < 3 * HR; r += NT) {
         halo[r * HW] = 0.f;
         halo[r * HW + HW - 1] = 0.f;
@@ -83,6 +83,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     float2* __restrict__ S = d.S;
     const int NJB = Dp >> 3;
     const __amdgpu_buffer_rsrc_t Srs = make_rsrc(S, (unsigned)(3 * H * Dp) * 8u);
+    const __amdgpu_buffer_rsrc_t Krs = make_rsrc(d.spec, (unsigned)(4 * H * H) * 4u);
     // byte offset of the spectrum of component c, column k, row j
     auto soff = [&](int c, int k, int j) { return ((((c * NJB + (j >> 3)) * H + k) << 3) + (j & 7)) * 8; };
     // row pass: item idx -> (row pair uu of the iteration, spectral column k)
@@ -97,7 +98,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     // the field kernel serves demag / rhs / energy at run time; the integrators are compiled per mode
     const int mode = (MODE == MODE_DEMAG) ? a.mode : MODE;
     // first Heun step index: from the handle's device counter when one is given
-    const unsigned long long step0 = (MODE == MODE_HEUN && a.step_ptr) ? *a.step_ptr : a.step0;
+    const unsigned long long step0 = (MODE == MODE_HEUN && a.step_ptr) ? *gbl(a.step_ptr) : a.step0;
 
     // ---- packed rows of a state into LDS (masked), columns [0, D)
     auto load_state_rows = [&](int b, const float* src) {
@@ -167,32 +168,38 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     // Kxx mx + Kxy my, y wave: Kxy mx + Kyy my, z wave: Kzz mz), with the kernel
     // spectra of those points loaded together with the column.
     constexpr bool KEEP = fft_whole_radix<P, R>();
-    struct ColIn {
-        float2 v[R];      // this lane's column values
+    struct ColV {
+        float2 v[R];          // this lane's column values
+    };
+    struct ColK {
         float k0[R], k1[R];   // kernel spectra at this lane's points (quarter-plane values)
     };
-    auto col_load = [&](int b, ColIn& c) {
+    // column values of tile b (zeros past the last column)
+    auto col_load_v = [&](int b, ColV& c) {
         const int kx = b * U + u;
         const bool valid = kx < H;
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const int i = t + j * Tf;
-            c.v[j] = (valid && i < D) ? bld2(Srs, soff(wave, kx, i)) : make_float2(0.f, 0.f);
+            c.v[j] = bld2(Srs, (valid && i < D) ? soff(wave, kx, i) : OOB);
         }
+    };
+    auto col_load_k = [&](int b, ColK& c) {
+        const int kx = b * U + u;
+        const bool valid = kx < H;
         // planes: 0 = xx, 1 = yy, 2 = xy, 3 = zz
         const int pl0 = wave == 0 ? 0 : wave == 1 ? 2 : 3;
         const int pl1 = wave == 0 ? 2 : 1;
-        const float* sp0 = d.spec + (size_t)pl0 * H * H + (size_t)(valid ? kx : 0) * H;
-        const float* sp1 = d.spec + (size_t)pl1 * H * H + (size_t)(valid ? kx : 0) * H;
+        const int o0 = (pl0 * H + kx) * H, o1 = (pl1 * H + kx) * H;
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const int ky = t + j * Tf;
             const int kq = ky <= P / 2 ? ky : P - ky;
-            c.k0[j] = valid ? sp0[kq] : 0.f;
-            c.k1[j] = (valid && wave < 2) ? sp1[kq] : 0.f;
+            c.k0[j] = bld1c(Krs, valid ? (o0 + kq) * 4 : OOB);
+            c.k1[j] = bld1c(Krs, (valid && wave < 2) ? (o1 + kq) * 4 : OOB);
         }
     };
-    auto col_compute = [&](int b, ColIn& c) {
+    auto col_compute = [&](int b, ColV& c, const ColK& kk) {
         const int kx = b * U + u;
         const bool valid = kx < H;
         fft_run<P, R, false>(c.v, mybuf, ltw, t);   // ends with a workgroup barrier
@@ -203,11 +210,11 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             const float sg = ky <= P / 2 ? 1.f : -1.f;   // K_xy is odd in ky
             const float2 A = BUF(wave == 2 ? 2 : 0, u)[pad16(ky)];
             if (wave == 2) {
-                v[j] = make_float2(c.k0[j] * A.x, c.k0[j] * A.y);
+                v[j] = make_float2(kk.k0[j] * A.x, kk.k0[j] * A.y);
             } else {
                 const float2 B = BUF(1, u)[pad16(ky)];
-                const float ka = wave == 0 ? c.k0[j] : sg * c.k0[j];
-                const float kb = wave == 0 ? sg * c.k1[j] : c.k1[j];
+                const float ka = wave == 0 ? kk.k0[j] : sg * kk.k0[j];
+                const float kb = wave == 0 ? sg * kk.k1[j] : kk.k1[j];
                 v[j] = make_float2(ka * A.x + kb * B.x, ka * A.y + kb * B.y);
             }
         }
@@ -217,23 +224,31 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
 #pragma unroll
             for (int j = 0; j < R; ++j) {
                 const int i = t + j * Tf;
-                if (valid && i < D) bst2(Srs, soff(wave, kx, i), v[j]);
+                bst2(Srs, (valid && i < D) ? soff(wave, kx, i) : OOB, v[j]);
             }
         } else {
             fft_run<P, R, true>(v, mybuf, ltw, t);
 #pragma unroll
             for (int j = 0; j < R; ++j) {
                 const int i = t + j * Tf;
-                if (valid && i < D) bst2(Srs, soff(wave, kx, i), mybuf[pad16(i)]);
+                bst2(Srs, (valid && i < D) ? soff(wave, kx, i) : OOB, mybuf[pad16(i)]);
             }
         }
     };
-    // all columns of this workgroup
+    // all columns of this workgroup; the column values of the next tile are
+    // loaded before the current tile is transformed, so their memory latency
+    // overlaps the transforms (tiles write only their own columns)
     auto column_pass = [&]() {
+        if (g >= n_cb) return;
+        ColV cur;
+        col_load_v(g, cur);
         for (int b = g; b < n_cb; b += G) {
-            ColIn c;
-            col_load(b, c);
-            col_compute(b, c);
+            ColK kk;
+            col_load_k(b, kk);
+            ColV nxt;
+            col_load_v(b + G, nxt);
+            col_compute(b, cur, kk);
+            cur = nxt;
         }
     };
 
@@ -251,10 +266,9 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             const int p = b * U + uu;
             const bool ok = idx < U * H && p < d.n_pairs;
             const int j0 = 2 * p;
-            const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-            sv[q].x = ok ? bld4(Srs, soff(0, k, j0)) : z4;
-            sv[q].y = ok ? bld4(Srs, soff(1, k, j0)) : z4;
-            sv[q].z = ok ? bld4(Srs, soff(2, k, j0)) : z4;
+            sv[q].x = bld4(Srs, ok ? soff(0, k, j0) : OOB);
+            sv[q].y = bld4(Srs, ok ? soff(1, k, j0) : OOB);
+            sv[q].z = bld4(Srs, ok ? soff(2, k, j0) : OOB);
         }
     };
     auto row_unpack_inverse = [&](const SRow (&sv)[IS]) {
@@ -301,7 +315,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             const int c = row / HR, rr = row - c * HR;
             const int j = 2 * b * U - 1 + rr;
             const bool ok = row < 3 * HR && i < D && j >= 0 && j < D && in_disk(j, i, D);
-            hv[q] = ok ? bld1(Yr, (c * DD + j * D + i) * 4) : 0.f;
+            hv[q] = bld1(Yr, ok ? (c * DD + j * D + i) * 4 : OOB);
         }
     };
     auto halo_store = [&](const float (&hv)[IH]) {
@@ -334,6 +348,8 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     Gath gv[IC];
     auto gather = [&](int b, int s) {
         const bool need_acc = (mode == MODE_RK4 && s > 0) || (mode == MODE_HEUN && s == 1);
+        const __amdgpu_buffer_rsrc_t Mrs = make_rsrc(m, (unsigned)(3 * DD) * 4u);
+        const __amdgpu_buffer_rsrc_t Ars = make_rsrc(d.acc, (unsigned)(3 * DD) * 4u);
 #pragma unroll
         for (int q = 0; q < IC; ++q) {
             const int idx = tid<OPQ>() + q * NT;
@@ -349,8 +365,8 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const int cell = c * DD + j * D + i;
-                    G_.y0[r][c] = (need_y0 && okc) ? ld_sh(m + cell) : 0.f;
-                    G_.ac[r][c] = (need_acc && okc) ? d.acc[cell] : 0.f;
+                    G_.y0[r][c] = bld1(Mrs, (need_y0 && okc) ? cell * 4 : OOB);
+                    G_.ac[r][c] = bld1c(Ars, (need_acc && okc) ? cell * 4 : OOB);
                 }
             }
         }
@@ -393,9 +409,9 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                 const float2 hxy = BUF(r, uu)[pad16(i)];
                 const float Hx = hxy.x, Hy = hxy.y, Hz = r == 0 ? hz2.x : hz2.y;
                 if (mode == MODE_DEMAG) {
-                    out[cell] = in ? Hx : 0.f;
-                    out[DD + cell] = in ? Hy : 0.f;
-                    out[2 * DD + cell] = in ? Hz : 0.f;
+                    gbl(out)[cell] = in ? Hx : 0.f;
+                    gbl(out)[DD + cell] = in ? Hy : 0.f;
+                    gbl(out)[2 * DD + cell] = in ? Hz : 0.f;
                     continue;
                 }
                 const float mx = col[r + 1][0], my = col[r + 1][1], mz = col[r + 1][2];
@@ -422,13 +438,13 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                     const float fy = py - al * (mz * px - mx * pz);
                     const float fz = pz - al * (mx * py - my * px);
                     if (mode == MODE_RHS) {
-                        out[cell] = in ? fx : 0.f;
-                        out[DD + cell] = in ? fy : 0.f;
-                        out[2 * DD + cell] = in ? fz : 0.f;
+                        gbl(out)[cell] = in ? fx : 0.f;
+                        gbl(out)[DD + cell] = in ? fy : 0.f;
+                        gbl(out)[2 * DD + cell] = in ? fz : 0.f;
                         continue;
                     }
                     if (recd) {
-                        float* rs = recd + ((size_t)(n * 4 + s) * 2) * 3 * DD + cell;
+                        GLOBAL_AS float* rs = gbl(recd) + ((size_t)(n * 4 + s) * 2) * 3 * DD + cell;
                         rs[0] = in ? mx : 0.f;
                         rs[DD] = in ? my : 0.f;
                         rs[2 * DD] = in ? mz : 0.f;
@@ -439,9 +455,9 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                     if (in) {
                         if (s < 3) {
                             const float w = (s == 0) ? 1.f : 2.f;
-                            d.acc[cell] = ac[r][0] + w * fx;
-                            d.acc[DD + cell] = ac[r][1] + w * fy;
-                            d.acc[2 * DD + cell] = ac[r][2] + w * fz;
+                            gbl(d.acc)[cell] = ac[r][0] + w * fx;
+                            gbl(d.acc)[DD + cell] = ac[r][1] + w * fy;
+                            gbl(d.acc)[2 * DD + cell] = ac[r][2] + w * fz;
                             const float h = (s == 2) ? dt : 0.5f * dt;
                             nx = y0[r][0] + h * fx;
                             ny = y0[r][1] + h * fy;
@@ -458,13 +474,12 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                                 nzv *= rn;
                             }
                             if (!(isfinite(nx) && isfinite(ny) && isfinite(nzv)))
-                                __hip_atomic_fetch_or(a.err, (int)ERR_NONFINITE, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
+                                raise_err(a.err, (int)ERR_NONFINITE);
                         }
                     }
                 } else if (in) {  // MODE_HEUN
                     if (recd) {
-                        float* rs = recd + ((size_t)(n * 2 + s) * 2) * 3 * DD + cell;
+                        GLOBAL_AS float* rs = gbl(recd) + ((size_t)(n * 2 + s) * 2) * 3 * DD + cell;
                         rs[0] = mx;
                         rs[DD] = my;
                         rs[2 * DD] = mz;
@@ -480,9 +495,9 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                     const float dy = py - al * (mz * px - mx * pz);
                     const float dz = pz - al * (mx * py - my * px);
                     if (s == 0) {
-                        d.acc[cell] = dx;
-                        d.acc[DD + cell] = dy;
-                        d.acc[2 * DD + cell] = dz;
+                        gbl(d.acc)[cell] = dx;
+                        gbl(d.acc)[DD + cell] = dy;
+                        gbl(d.acc)[2 * DD + cell] = dz;
                         nx = mx + dx;
                         ny = my + dy;
                         nzv = mz + dz;
@@ -497,8 +512,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                             nzv *= rn;
                         }
                         if (!(isfinite(nx) && isfinite(ny) && isfinite(nzv)))
-                            __hip_atomic_fetch_or(a.err, (int)ERR_NONFINITE, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
+                            raise_err(a.err, (int)ERR_NONFINITE);
                     }
                 }
                 // integrators: store the next stage state (zero outside the disk)
@@ -535,9 +549,9 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         const int sf = fin ? 3 - (int)((k - 1) % 4) : 0, ss = sta ? 3 - (int)(k % 4) : 0;
         const float* Bf = ((k - 1) & 1) ? d.yb : d.ya;      // bbar of the finishing stage
         float* Bs = (k & 1) ? d.yb : d.ya;                  // bbar of the starting stage
-        const float* Yrec = recd + ((size_t)(ns * 4 + ss) * 2) * 3 * DD;
-        const float* Hrec = Yrec + 3 * DD;
-        const float* Hfin = recd + ((size_t)(nf * 4 + sf) * 2 + 1) * 3 * DD;
+        const GLOBAL_AS float* Yrec = gbl(recd) + ((size_t)(ns * 4 + ss) * 2) * 3 * DD;
+        const GLOBAL_AS float* Hrec = Yrec + 3 * DD;
+        const GLOBAL_AS float* Hfin = gbl(recd) + ((size_t)(nf * 4 + sf) * 2 + 1) * 3 * DD;
         for (int idx = tid<OPQ>(); idx < U * D; idx += NT) {
             const int uu = idx / D, i = idx - uu * D;
             const int p = b * U + uu;
@@ -569,7 +583,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                     yl[r][c] = (sta && okl) ? Yrec[cell - 1] : 0.f;
                     yr[r][c] = (sta && okr) ? Yrec[cell + 1] : 0.f;
                     ax[r][c] = (fin && okc) ? d.aux[cell] : 0.f;
-                    ac[r][c] = (fin && okc) ? d.acc[cell] : 0.f;
+                    ac[r][c] = (fin && okc) ? gbl(d.acc)[cell] : 0.f;
                     hf[r][c] = (fin && okc) ? Hfin[cell] : 0.f;
                     hs[r][c] = (sta && okc) ? Hrec[cell] : 0.f;
                     yb0[r][c] = (sta && okc) ? ld_sh(m + cell) : 0.f;
@@ -613,13 +627,13 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                         }
                     } else {
 #pragma unroll
-                        for (int c = 0; c < 3; ++c) d.acc[c * DD + cell] = accn[c];
+                        for (int c = 0; c < 3; ++c) gbl(d.acc)[c * DD + cell] = accn[c];
                     }
                 }
                 if (sta) {
                     if (ss == 3) {
 #pragma unroll
-                        for (int c = 0; c < 3; ++c) d.acc[c * DD + cell] = ybar[c];
+                        for (int c = 0; c < 3; ++c) gbl(d.acc)[c * DD + cell] = ybar[c];
                     }
                     const float w = (ss == 3 || ss == 0) ? dt * (1.0f / 6.0f) : dt * (1.0f / 3.0f);
                     const float v = (ss == 3) ? 0.f : (ss == 2) ? dt : 0.5f * dt;
@@ -687,10 +701,10 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         const int sf = fin ? 1 - (int)((k - 1) % 2) : 0, ss = sta ? 1 - (int)(k % 2) : 0;
         const float* Bf = ((k - 1) & 1) ? d.yb : d.ya;      // gbar of the finishing stage
         float* Bs = (k & 1) ? d.yb : d.ya;                  // gbar of the starting stage
-        const float* Yrec = recd + ((size_t)(ns * 2 + ss) * 2) * 3 * DD;
-        const float* Hrec = Yrec + 3 * DD;
-        const float* Y0rec = recd + ((size_t)(ns * 2) * 2) * 3 * DD;      // m_ns (stage 1 state)
-        const float* Hfin = recd + ((size_t)(nf * 2 + sf) * 2 + 1) * 3 * DD;
+        const GLOBAL_AS float* Yrec = gbl(recd) + ((size_t)(ns * 2 + ss) * 2) * 3 * DD;
+        const GLOBAL_AS float* Hrec = Yrec + 3 * DD;
+        const GLOBAL_AS float* Y0rec = gbl(recd) + ((size_t)(ns * 2) * 2) * 3 * DD;      // m_ns (stage 1 state)
+        const GLOBAL_AS float* Hfin = gbl(recd) + ((size_t)(nf * 2 + sf) * 2 + 1) * 3 * DD;
         const float sg = pr.sigma, dsg = pr.dsigma;
         for (int idx = tid<OPQ>(); idx < U * D; idx += NT) {
             const int uu = idx / D, i = idx - uu * D;
@@ -738,7 +752,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                 if (fin && sf == 0) {                // step nf complete: m_nf bar
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        const float v = d.acc[c * DD + cell] + fin_tot[c];
+                        const float v = gbl(d.acc)[c * DD + cell] + fin_tot[c];
                         st_sh(m + c * DD + cell, v);
                         ybar[c] = v;
                     }
@@ -781,7 +795,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                         yb[2] = (yb[2] - pu * uz) * inv;
                     }
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) d.acc[c * DD + cell] = yb[c];
+                    for (int c = 0; c < 3; ++c) gbl(d.acc)[c * DD + cell] = yb[c];
                     cx = 0.5f * yb[0];
                     cy = 0.5f * yb[1];
                     cz = 0.5f * yb[2];
@@ -790,8 +804,8 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                     float yb[3];
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        yb[c] = d.acc[c * DD + cell];
-                        d.acc[c * DD + cell] = yb[c] + fin_tot[c];
+                        yb[c] = gbl(d.acc)[c * DD + cell];
+                        gbl(d.acc)[c * DD + cell] = yb[c] + fin_tot[c];
                     }
                     cx = fin_tot[0] + 0.5f * yb[0];
                     cy = fin_tot[1] + 0.5f * yb[1];
@@ -922,7 +936,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             const int q = tid<OPQ>();
             double acc = 0.0;
             for (int w = 0; w < 3 * UG; ++w) acc += red[w][q];
-            d.part[g * PART_STRIDE + q] = acc;
+            gbl(d.part)[g * PART_STRIDE + q] = acc;
         }
     };
 
@@ -1003,7 +1017,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                 }
         }
         if (g == 0 && tid<OPQ>() == 0) {
-            double* o = a.relax_out + 8 * d.k;
+            GLOBAL_AS double* o = gbl(a.relax_out) + 8 * d.k;
             o[0] = lx;
             o[1] = ly;
             o[2] = (double)sweep;
