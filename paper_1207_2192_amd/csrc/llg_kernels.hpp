@@ -1066,6 +1066,29 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             cell_update(b, s, n, Yn);
         };
 
+        // all row iterations of a stage: the staged rows and row spectra of the
+        // next iteration are loaded after the cell update of the current one, so
+        // that they are in flight during its forward transforms and stores; the
+        // start state and accumulator are loaded at the top of the iteration
+        // (iterations touch disjoint rows of the spectra and of the states they
+        // write; a load past the last iteration reads zeros or unused rows)
+        auto row_pass = [&](int s, long long n, const float* Ys, float* Yn, bool fwd) {
+            if (g >= n_rb) return;
+            float hv[IH];
+            SRow sv[IS];
+            halo_load(g, Ys, hv);
+            row_load(g, sv);
+            for (int b = g; b < n_rb; b += G) {
+                gather(b, s);
+                halo_store(hv);
+                row_unpack_inverse(sv);
+                cell_update(b, s, n, Yn);
+                halo_load(b + G, Ys, hv);
+                row_load(b + G, sv);
+                if (fwd) row_forward_store(b);
+            }
+        };
+
         if constexpr (MODE == MODE_DEMAG) {
             column_pass();
             if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
@@ -1088,10 +1111,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                         Ys = (s == 0) ? m : d.ya;
                         Yn = (s == 0) ? d.ya : m;
                     }
-                    for (int b = g; b < n_rb; b += G) {
-                        row_step(b, s, n, Ys, Yn);
-                        if (!last) row_forward_store(b);
-                    }
+                    row_pass(s, n, Ys, Yn, !last);
                     if (!last && !group_barrier(d.bar, ++epoch * G, G, a.err)) return;
                 }
             }
