@@ -120,15 +120,16 @@ __device__ __forceinline__ void thermal_normals_pair(unsigned long long seed, un
     philox4x32_10(a0, a1, a2, a3, k0, k1);
     uint32_t b0 = s0, b1 = s1, b2 = (uint32_t)(2 * q + 1), b3 = rep;
     philox4x32_10(b0, b1, b2, b3, k0, k1);
-    const float ra = sqrtf(-2.0f * logf(u24(a0)));
-    const float rb = sqrtf(-2.0f * logf(u24(a2)));
-    const float rc = sqrtf(-2.0f * logf(u24(b0)));
-    float sa, ca, sb, cb, sc, cc;
-    sincospif(2.0f * u24(a1), &sa, &ca);
-    sincospif(2.0f * u24(a3), &sb, &cb);
-    sincospif(2.0f * u24(b1), &sc, &cc);
-    even = make_float3(ra * ca, ra * sa, rb * cb);
-    odd = make_float3(rb * sb, rc * cc, rc * sc);
+    // hardware transcendentals: log2, square root, and sine / cosine of an
+    // angle given in revolutions (sin(2 pi u) for u in (0, 1)); each is within
+    // a few ulp, far inside what the noise amplitude lets reach the state
+    constexpr float M2LN2 = -1.38629436111989061f;   // -2 ln 2:  -2 ln u = -2 ln 2 log2 u
+    const float ra = __builtin_amdgcn_sqrtf(M2LN2 * __builtin_amdgcn_logf(u24(a0)));
+    const float rb = __builtin_amdgcn_sqrtf(M2LN2 * __builtin_amdgcn_logf(u24(a2)));
+    const float rc = __builtin_amdgcn_sqrtf(M2LN2 * __builtin_amdgcn_logf(u24(b0)));
+    const float ta = u24(a1), tb = u24(a3), tc = u24(b1);
+    even = make_float3(ra * __builtin_amdgcn_cosf(ta), ra * __builtin_amdgcn_sinf(ta), rb * __builtin_amdgcn_cosf(tb));
+    odd = make_float3(rb * __builtin_amdgcn_sinf(tb), rc * __builtin_amdgcn_cosf(tc), rc * __builtin_amdgcn_sinf(tc));
 }
 
 // ---------------------------------------------------------------- shared buffers
