@@ -88,7 +88,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--wg", type=int, default=0, help="workgroups for the disk (0 = library choice)")
     ap.add_argument("--ug", type=int, default=0, help="wavefront groups per workgroup (0 = library choice)")
-    ap.add_argument("--radix", type=int, default=0, help="radix policy for --ug/--wg (0 or 1)")
+    ap.add_argument("--radix", type=int, default=0, help="transform policy for --ug/--wg (0..3: bit 0 radix 8, bit 1 lane-group columns)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default launch plan")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"])
     ap.add_argument("--plain", action="store_true", help="loop over single-disk handles instead of one batch")

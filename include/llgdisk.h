@@ -113,23 +113,26 @@ int llg_disk_workgroups(llg_disk h, int k);
 
 /* Re-plan the persistent launch of h (host; synchronises the device):
  * unit_groups = 1, 2 or 4 groups of three wavefronts per workgroup (each
- * group carries one transform per field component at a time), radix_policy
- * = 0 (radix-4 LDS stages; radix 8 at P = 512) or 1 (radix 8 everywhere), and
- * the number of workgroups per disk (wg_per_disk, host, n entries; NULL = the
- * library's choice).  Results do not depend on the plan beyond float rounding
- * of the radix schedule. */
+ * group carries one transform per field component at a time), the transform
+ * policy radix_policy = 0..3 (bit 0: radix-8 LDS stages everywhere, else
+ * radix 4 below P = 512; bit 1: each lane group transforms all three
+ * components of one spectral column, else one wavefront per component; the
+ * adjoint and relaxation kernels ignore bit 1), and the number of workgroups
+ * per disk (wg_per_disk, host, n entries; NULL = the library's choice).
+ * Results do not depend on the plan beyond float rounding of the radix
+ * schedule. */
 int llg_tune(llg_disk h, int unit_groups, int radix_policy, const int* wg_per_disk);
 
 /* Autotuner: times llg_rk4_step (integrator 0) or llg_heun_step (1) for
  * probe_steps steps on a private copy of m (device) under every candidate plan
- * (unit groups 1/2/4 x radix policy 0/1 x the library's workgroup counts
+ * (unit groups 1/2/4 x transform policy 0..3 x the library's workgroup counts
  * scaled by 1, 1/2, 1/4) and keeps the fastest.  *best_us (host) receives its
  * time per step in microseconds.  Synchronises; m is not modified. */
 int llg_autotune(llg_disk h, const float* m, const llg_params* p, int integrator, long long probe_steps,
                  void* stream, double* best_us);
 
 /* Current launch shape (host): unit groups, total workgroups, threads per
- * workgroup, radix policy (any pointer may be NULL). */
+ * workgroup, transform policy (any pointer may be NULL). */
 int llg_launch_shape(llg_disk h, int* unit_groups, int* workgroups, int* threads, int* radix_policy);
 
 /* Demagnetisation field H^M / Ms of state m (Sec. II.B): H[k] = sum over the

@@ -114,7 +114,7 @@ class Disk:
         return best.value
 
     def launch_shape(self):
-        """(unit groups, workgroups, threads per workgroup, radix policy)."""
+        """(unit groups, workgroups, threads per workgroup, transform policy)."""
         ug, nwg, nt, rs = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         check(_lib.load().llg_launch_shape(self._h, ctypes.byref(ug), ctypes.byref(nwg), ctypes.byref(nt),
                                            ctypes.byref(rs)), "llg_launch_shape")

@@ -121,13 +121,15 @@ constexpr int padded_len() { return P + P / 16; }
 // workgroup barrier, so every lane of the workgroup must call this the same
 // number of times.
 // With KEEP (only when P is a power of R) the last stage is not written back:
-// v[j] then holds X[t + j*(P/R)] and no closing barrier is issued.
+// v[j] then holds X[t + j*(P/R)] and no closing barrier is issued.  Without
+// WGSYNC the buffer is private to the calling wavefront, and the closing
+// barrier is a wavefront-scope fence.
 template <int P, int R>
 constexpr bool fft_whole_radix() {
     return (1 << ((ilog2(P) / ilog2(R)) * ilog2(R))) == P;
 }
 
-template <int P, int R, bool INV, bool KEEP = false>
+template <int P, int R, bool INV, bool KEEP = false, bool WGSYNC = true>
 __device__ __forceinline__ void fft_run(float2 (&v)[R], float2* buf, const float2* tw, int t) {
     constexpr int Tf = P / R;
     constexpr int LOGR = ilog2(R);
@@ -154,7 +156,7 @@ __device__ __forceinline__ void fft_run(float2 (&v)[R], float2* buf, const float
         wave_sync();
 #pragma unroll
         for (int j = 0; j < R; ++j) buf[pad16(base + j * Ns)] = v[j];
-        if (REM == 1 && s == NFULL - 1)
+        if (WGSYNC && REM == 1 && s == NFULL - 1)
             __syncthreads();
         else
             wave_sync();
@@ -186,7 +188,10 @@ __device__ __forceinline__ void fft_run(float2 (&v)[R], float2* buf, const float
 #pragma unroll
             for (int j = 0; j < REM; ++j) buf[pad16(base + j * Ns)] = u[q * REM + j];
         }
-        __syncthreads();
+        if constexpr (WGSYNC)
+            __syncthreads();
+        else
+            wave_sync();
     }
 }
 

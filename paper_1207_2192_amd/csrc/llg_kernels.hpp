@@ -42,7 +42,7 @@ struct RowTile {
     static constexpr int floats = 3 * HR * HW;
 };
 
-template <int P, int R, int UG, int MODE, bool LARGE>
+template <int P, int R, int UG, int MODE, bool LARGE, bool SLOT>
 __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, const DiskPrm& pr, int g,
                                          float2* lds, float2* ltw, float* halo) {
     constexpr int Tf = P / R;
@@ -93,7 +93,8 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         uu = (rest / H) * UQ + uq;
     };
     const int n_rb = (d.n_pairs + U - 1) / U;
-    const int n_cb = (H + U - 1) / U;
+    const int n_cb = (H + 3 * U - 1) / (3 * U);   // column tiles of 3U columns (one per transform slot)
+    const int n_cb_split = (H + U - 1) / U;       // column tiles of U columns (one wave per component)
     unsigned int epoch = 0;
     // the field kernel serves demag / rhs / energy at run time; the integrators are compiled per mode
     const int mode = (MODE == MODE_DEMAG) ? a.mode : MODE;
@@ -162,12 +163,103 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         __syncthreads();
     };
 
-    // ---- column kx: forward FFT along y, kernel multiply, inverse FFT along y
-    // The multiply is fused into the loads of the inverse transform: each lane
-    // forms its own inputs ky = t + j*Tf from the three forward spectra (x wave:
-    // Kxx mx + Kxy my, y wave: Kxy mx + Kyy my, z wave: Kzz mz), with the kernel
-    // spectra of those points loaded together with the column.
+    // ---- column phase, one transform slot per column (for disks with several
+    // column tiles per workgroup): each transform slot (lane group) takes one spectral
+    // column kx with all three components: forward FFTs along y, the kernel
+    // multiply in registers (x: Kxx mx + Kxy my, y: Kxy mx + Kyy my, z: Kzz mz),
+    // inverse FFTs, and stores of the D rows of the disk.  A slot's LDS buffer
+    // belongs to its wavefront alone, so the phase has no workgroup barrier;
+    // where P is a power of the radix the forward results stay in registers in
+    // exactly the order the inverse transform takes them.
     constexpr bool KEEP = fft_whole_radix<P, R>();
+    constexpr int NSLOT = 3 * U;
+    const int slot = wave * U + u;
+    auto col_fwd = [&](float2 (&v)[R]) {
+        __builtin_amdgcn_sched_barrier(0);   // one transform at a time: bounds the live registers
+        if constexpr (KEEP) {
+            fft_run<P, R, false, true>(v, mybuf, ltw, t);
+        } else {
+            fft_run<P, R, false, false, false>(v, mybuf, ltw, t);
+#pragma unroll
+            for (int j = 0; j < R; ++j) v[j] = mybuf[pad16(t + j * Tf)];
+            wave_sync();
+        }
+    };
+    auto col_inv_store = [&](int c, int kx, bool valid, float2 (&v)[R]) {
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (KEEP) {
+            fft_run<P, R, true, true>(v, mybuf, ltw, t);   // v[j] = column value at row t + j*Tf
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int i = t + j * Tf;
+                bst2(Srs, (valid && i < D) ? soff(c, kx, i) : OOB, v[j]);
+            }
+        } else {
+            fft_run<P, R, true, false, false>(v, mybuf, ltw, t);
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int i = t + j * Tf;
+                bst2(Srs, (valid && i < D) ? soff(c, kx, i) : OOB, mybuf[pad16(i)]);
+            }
+            wave_sync();
+        }
+    };
+    // all column tiles of this workgroup: z first (it needs only Kzz), while the
+    // x and y columns are still arriving
+    auto column_pass_slot = [&]() {
+        for (int b = g; b < n_cb; b += G) {
+            const int kx = b * NSLOT + slot;
+            const bool valid = kx < H;
+            float2 X[R], Y[R], Z[R];
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int i = t + j * Tf;
+                Z[j] = bld2(Srs, (valid && i < D) ? soff(2, kx, i) : OOB);
+            }
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int i = t + j * Tf;
+                const bool ok = valid && i < D;
+                X[j] = bld2(Srs, ok ? soff(0, kx, i) : OOB);
+                Y[j] = bld2(Srs, ok ? soff(1, kx, i) : OOB);
+            }
+            // kernel spectra at this lane's points: quarter-plane planes 0 = xx, 1 = yy, 2 = xy, 3 = zz
+            auto kidx = [&](int j) {
+                const int ky = t + j * Tf;
+                return kx * H + (ky <= P / 2 ? ky : P - ky);
+            };
+            col_fwd(Z);
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const float kzz = bld1c(Krs, valid ? (3 * H * H + kidx(j)) * 4 : OOB);
+                Z[j] = make_float2(kzz * Z[j].x, kzz * Z[j].y);
+            }
+            col_inv_store(2, kx, valid, Z);
+            col_fwd(X);
+            col_fwd(Y);
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int o = kidx(j);
+                const float kxx = bld1c(Krs, valid ? o * 4 : OOB);
+                const float kyy = bld1c(Krs, valid ? (H * H + o) * 4 : OOB);
+                const float kxy = bld1c(Krs, valid ? (2 * H * H + o) * 4 : OOB);
+                const float axy = t + j * Tf <= P / 2 ? kxy : -kxy;   // K_xy is odd in ky
+                const float2 x = X[j], y = Y[j];
+                X[j] = make_float2(kxx * x.x + axy * y.x, kxx * x.y + axy * y.y);
+                Y[j] = make_float2(axy * x.x + kyy * y.x, axy * x.y + kyy * y.y);
+            }
+            col_inv_store(0, kx, valid, X);
+            col_inv_store(1, kx, valid, Y);
+        }
+    };
+
+    // ---- column phase, one wavefront per component (for disks with more
+    // workgroups than column tiles): tile b holds the U columns kx = b*U + u and
+    // wave c of a group transforms component c.  The multiply is fused into the
+    // loads of the inverse transform: each lane forms its own inputs ky = t + j*Tf
+    // from the three forward spectra (x wave: Kxx mx + Kxy my, y wave: Kxy mx +
+    // Kyy my, z wave: Kzz mz), with the kernel spectra of those points loaded
+    // together with the column.
     struct ColV {
         float2 v[R];          // this lane's column values
     };
@@ -235,14 +327,14 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             }
         }
     };
-    // all columns of this workgroup; the column values of the next tile are
+    // all column tiles of this workgroup; the column values of the next tile are
     // loaded before the current tile is transformed, so their memory latency
     // overlaps the transforms (tiles write only their own columns)
-    auto column_pass = [&]() {
-        if (g >= n_cb) return;
+    auto column_pass_split = [&]() {
+        if (g >= n_cb_split) return;
         ColV cur;
         col_load_v(g, cur);
-        for (int b = g; b < n_cb; b += G) {
+        for (int b = g; b < n_cb_split; b += G) {
             ColK kk;
             col_load_k(b, kk);
             ColV nxt;
@@ -250,6 +342,17 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             col_compute(b, cur, kk);
             cur = nxt;
         }
+    };
+
+    // The column strategy is part of the transform policy: one wavefront per
+    // component (more lanes per column, for disks with few column tiles per
+    // workgroup) or one lane group per column (less LDS traffic, no workgroup
+    // barriers, for many tiles per workgroup).
+    auto column_pass = [&]() {
+        if constexpr (SLOT)
+            column_pass_slot();
+        else
+            column_pass_split();
     };
 
     // ---- rebuild the full-length row spectra of a pair and transform back along x
@@ -1120,60 +1223,80 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
 #undef BUF
 }
 
-// Radix schedule of the LDS transforms: policy 0 uses radix 4 (radix 8 at
-// P = 512, where 64 lanes must carry 512 points); policy 1 uses radix 8 for
-// every size.  The tuner picks the policy per handle.
-template <int P, int RSEL>
+// Transform policy (the tuner picks one per handle): bit 0 selects the radix
+// of the LDS transforms (0: radix 4, except radix 8 at P = 512 where 64 lanes
+// must carry 512 points; 1: radix 8 for every size); bit 1 selects the column
+// strategy (0: one wavefront per component, 1: one lane group per column with
+// all three components).  The adjoint and relaxation kernels always use the
+// first column strategy.
+template <int P, int POL>
 struct Radix {
-    static constexpr int value = (RSEL == 1 || P == 512) ? 8 : 4;
+    static constexpr int value = ((POL & 1) == 1 || P == 512) ? 8 : 4;
 };
+constexpr bool column_slots(int POL, int MODE) {
+    return (POL & 2) != 0 && MODE != MODE_RK4_VJP && MODE != MODE_HEUN_VJP && MODE != MODE_RELAX;
+}
 
-// One persistent kernel per (workgroup shape UG, radix policy RSEL, mode,
+// One persistent kernel per (workgroup shape UG, transform policy POL, mode,
 // largest FFT size PMAX of the handle): each instance carries only the code
 // and registers of its own path.  MODE_DEMAG stands for the field kernel
 // (demag, rhs and energy, chosen at run time).
-template <int UG, int RSEL>
+template <int UG, int POL>
 constexpr int halo_floats(int PMAX) {
-    int n = RowTile<64, Radix<64, RSEL>::value, UG>::floats;
-    n = n > RowTile<128, Radix<128, RSEL>::value, UG>::floats ? n : RowTile<128, Radix<128, RSEL>::value, UG>::floats;
-    n = n > RowTile<256, Radix<256, RSEL>::value, UG>::floats ? n : RowTile<256, Radix<256, RSEL>::value, UG>::floats;
+    int n = RowTile<64, Radix<64, POL>::value, UG>::floats;
+    n = n > RowTile<128, Radix<128, POL>::value, UG>::floats ? n : RowTile<128, Radix<128, POL>::value, UG>::floats;
+    n = n > RowTile<256, Radix<256, POL>::value, UG>::floats ? n : RowTile<256, Radix<256, POL>::value, UG>::floats;
     if (PMAX >= 512)
-        n = n > RowTile<512, Radix<512, RSEL>::value, UG>::floats ? n : RowTile<512, Radix<512, RSEL>::value, UG>::floats;
+        n = n > RowTile<512, Radix<512, POL>::value, UG>::floats ? n : RowTile<512, Radix<512, POL>::value, UG>::floats;
     return n;
 }
 
-template <int UG, int RSEL, int MODE, int PMAX>
-__global__ __launch_bounds__(WG_THREADS* UG) void llg_persistent(KArgs a) {
+// The integrators keep three wavefronts per SIMD resident (the register
+// budget the compiler must meet); the other modes take what they need.
+constexpr int min_waves_per_simd(int mode) { return (mode == MODE_RK4 || mode == MODE_HEUN) ? 3 : 1; }
+
+template <int UG, int POL, int MODE, int PMAX>
+__global__ __launch_bounds__(WG_THREADS* UG) __attribute__((amdgpu_waves_per_eu(min_waves_per_simd(MODE))))
+void llg_persistent(KArgs a) {
     __shared__ float2 lds[LDS_FFT * UG];
     __shared__ float2 ltw[MAX_P];
-    __shared__ float halo[halo_floats<UG, RSEL>(PMAX)];
+    __shared__ float halo[halo_floats<UG, POL>(PMAX)];
     const int wg = blockIdx.x;
     const int di = a.wg2disk[wg];
     if (di < 0) return;
     const int g = a.wg2local[wg];
     const DiskDesc d = a.disks[di];
     const DiskPrm pr = a.prm[di];
+    constexpr bool L = PMAX >= 512, SL = column_slots(POL, MODE);
     switch (d.P) {
-        case 64: run_disk<64, Radix<64, RSEL>::value, UG, MODE, (PMAX >= 512)>(a, d, pr, g, lds, ltw, halo); break;
-        case 128: run_disk<128, Radix<128, RSEL>::value, UG, MODE, (PMAX >= 512)>(a, d, pr, g, lds, ltw, halo); break;
-        case 256: run_disk<256, Radix<256, RSEL>::value, UG, MODE, (PMAX >= 512)>(a, d, pr, g, lds, ltw, halo); break;
+        case 64: run_disk<64, Radix<64, POL>::value, UG, MODE, L, SL>(a, d, pr, g, lds, ltw, halo); break;
+        case 128: run_disk<128, Radix<128, POL>::value, UG, MODE, L, SL>(a, d, pr, g, lds, ltw, halo); break;
+        case 256: run_disk<256, Radix<256, POL>::value, UG, MODE, L, SL>(a, d, pr, g, lds, ltw, halo); break;
         case 512:
-            if constexpr (PMAX >= 512) run_disk<512, Radix<512, RSEL>::value, UG, MODE, (PMAX >= 512)>(a, d, pr, g, lds, ltw, halo);
+            if constexpr (PMAX >= 512) run_disk<512, Radix<512, POL>::value, UG, MODE, L, SL>(a, d, pr, g, lds, ltw, halo);
             break;
         default: break;
     }
 }
 
-// Kernel pointer of the instance for (UG, RSEL, PMAX) of one mode.
+// Kernel pointer of the instance for (UG, POL, PMAX) of one mode; modes without
+// the lane-group column strategy share the instances of policies 0 and 1.
 template <int MODE>
-const void* persistent_instance(int UG, int RSEL, int PMAX) {
-#define LLG_INST(ug, rs, pm)                                   \
-    if (UG == ug && RSEL == rs && PMAX == pm)                  \
-        return reinterpret_cast<const void*>(llg_persistent<ug, rs, MODE, pm>);
+const void* persistent_instance(int UG, int POL, int PMAX) {
+#define LLG_INST(ug, pl, pm)                                   \
+    if (UG == ug && POL == pl && PMAX == pm)                   \
+        return reinterpret_cast<const void*>(llg_persistent<ug, pl, MODE, pm>);
+    if (!column_slots(POL, MODE)) POL &= 1;
     LLG_INST(1, 0, 256) LLG_INST(2, 0, 256) LLG_INST(4, 0, 256)
     LLG_INST(1, 1, 256) LLG_INST(2, 1, 256) LLG_INST(4, 1, 256)
     LLG_INST(1, 0, 512) LLG_INST(2, 0, 512) LLG_INST(4, 0, 512)
     LLG_INST(1, 1, 512) LLG_INST(2, 1, 512) LLG_INST(4, 1, 512)
+    if constexpr (column_slots(2, MODE)) {
+        LLG_INST(1, 2, 256) LLG_INST(2, 2, 256) LLG_INST(4, 2, 256)
+        LLG_INST(1, 3, 256) LLG_INST(2, 3, 256) LLG_INST(4, 3, 256)
+        LLG_INST(1, 2, 512) LLG_INST(2, 2, 512) LLG_INST(4, 2, 512)
+        LLG_INST(1, 3, 512) LLG_INST(2, 3, 512) LLG_INST(4, 3, 512)
+    }
 #undef LLG_INST
     return nullptr;
 }

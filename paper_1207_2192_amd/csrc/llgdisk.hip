@@ -139,7 +139,10 @@ std::vector<unsigned char> disk_mask(int D, int* n_cells) {
     return m;
 }
 
-int radix_for(int P, int RSEL) { return (RSEL == 1 || P == 512) ? 8 : 4; }
+// Transform policy: bit 0 = radix 8 everywhere (else radix 4 below P = 512),
+// bit 1 = one lane group per column with all three components (else one
+// wavefront per component).
+int radix_for(int P, int RSEL) { return ((RSEL & 1) == 1 || P == 512) ? 8 : 4; }
 
 }  // namespace
 
@@ -173,7 +176,7 @@ struct llg_disk_s {
     unsigned long long* step_dev = nullptr;   // Heun step counter (LLG_STEP_COUNTER)
     unsigned plan_modes = 0;          // modes whose co-residency the current plan was checked for
     int UG = 1;                       // wavefront groups per workgroup of the persistent launch
-    int RSEL = 0;                     // radix policy of the LDS transforms
+    int RSEL = 0;                     // transform policy (radix and column strategy)
     int PMAX = 256;                   // largest FFT size of the handle's disks (kernel instance)
     std::vector<DiskDesc> desc;       // host copy of the descriptors
 
@@ -281,13 +284,15 @@ int default_unit_groups(llg_disk) {
 // Without explicit counts the plan minimises the slowest disk's estimated
 // stage time within a budget of scale x the co-resident workgroups: disk k on
 // G workgroups takes ceil(ncb/G) column and ceil(nrb/G) row iterations of cost
-// U P log2 P each plus, for G > 1, two group barriers (2500 in the same units:
-// the measured ratio of a barrier to a single-transform P = 256 column
-// iteration); the smallest target T whose per-disk counts (the fewest
-// workgroups that meet T) fit the budget is found by bisection.
+// U P log2 P each (with lane-group columns, ceil(ncb3/G) column iterations of
+// three times that, ncb3 = tiles of 3U columns) plus, for G > 1, two group
+// barriers (2500 in the same units: the measured ratio of a barrier to a
+// single-transform P = 256 column iteration); the smallest target T whose
+// per-disk counts (the fewest workgroups that meet T) fit the budget is found
+// by bisection.
 int plan(llg_disk h, int UG, int RSEL, const int* wg_per_disk, unsigned modes = ALL_MODES, double scale = 1.0) {
     if (UG != 1 && UG != 2 && UG != 4) return fail(LLG_EINVAL, "unit groups must be 1, 2 or 4");
-    if (RSEL != 0 && RSEL != 1) return fail(LLG_EINVAL, "radix policy must be 0 or 1");
+    if (RSEL < 0 || RSEL > 3) return fail(LLG_EINVAL, "transform policy must be 0, 1, 2 or 3");
     const int n = h->n;
     int cap = 0;
     int rc = max_coresident_workgroups(UG, RSEL, h->PMAX, &cap, modes);
@@ -299,14 +304,15 @@ int plan(llg_disk h, int UG, int RSEL, const int* wg_per_disk, unsigned modes = 
         const int U = units_per_wg(P, UG, RSEL);
         const int H = P / 2 + 1;
         const int n_pairs = (D + 1) / 2;
-        ncb[k] = (H + U - 1) / U;
+        ncb[k] = (RSEL & 2) ? (H + 3 * U - 1) / (3 * U) : (H + U - 1) / U;
         nrb[k] = (n_pairs + U - 1) / U;
         useful[k] = std::max(ncb[k], nrb[k]);
         work[k] = (double)(n_pairs + H) * P * std::log2((double)P);
         iter[k] = (double)U * P * std::log2((double)P);
     }
+    const int col_weight = (RSEL & 2) ? 3 : 1;
     auto stage_time = [&](int k, int g) {
-        return ((ncb[k] + g - 1) / g + (nrb[k] + g - 1) / g) * iter[k] + (g > 1 ? 5000.0 : 0.0);
+        return (col_weight * ((ncb[k] + g - 1) / g) + (nrb[k] + g - 1) / g) * iter[k] + (g > 1 ? 5000.0 : 0.0);
     };
     // fewest workgroups for disk k that meet the target T (or all useful ones)
     auto g_for = [&](int k, double T) {
@@ -730,12 +736,12 @@ int llg_autotune(llg_disk h, const float* m, const llg_params* p, int integrator
     const int mode = integrator == 0 ? MODE_RK4 : MODE_HEUN;
     llg_params* pp = const_cast<llg_params*>(p);
     if ((rc = upload_params(h, pp, st))) return rc;
-    // candidate plans: unit groups x radix policy x workgroup scale
+    // candidate plans: unit groups x transform policy x workgroup scale
     std::vector<int> base(h->n);
     struct Cand { int UG, RSEL; double scale; };
     std::vector<Cand> cands;
     for (int ug : {1, 2, 4})
-        for (int rs : {0, 1})
+        for (int rs : {0, 1, 2, 3})
             for (double sc : {1.0, 0.5, 0.25}) cands.push_back({ug, rs, sc});
     double best = 1e300;
     Cand bestc{h->UG, h->RSEL, 1.0};

@@ -21,10 +21,13 @@ def dev(a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda").reshape(-1).contiguous()
 
 
-@pytest.mark.parametrize("R,L,nsteps", [(15.0, 5.0, 3), (30.0, 10.0, 5), (61.0, 12.0, 2)])
-def test_rk4_vjp_matches_oracle(R, L, nsteps):
+@pytest.mark.parametrize("R,L,nsteps,pol", [(15.0, 5.0, 3, 0), (30.0, 10.0, 5, 0), (61.0, 12.0, 2, 0),
+                                            (30.0, 10.0, 5, 3)])
+def test_rk4_vjp_matches_oracle(R, L, nsteps, pol):
+    # pol 3: the recording integrator runs lane-group columns, the adjoint kernel its own strategy
     from paper_1207_2192_amd import Disk, LLGParams
     disk = Disk.build(R, L)
+    disk.tune(1, None, pol)
     D = disk.D[0]
     od = oracle.Disk(R, L)
     m0 = li.smooth_random_field(D, 4)

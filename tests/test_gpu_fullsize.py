@@ -15,11 +15,12 @@ pytestmark = pytest.mark.gpu
 C_PY = 0.14298555
 
 
-def test_heun_replicas_full_size():
+@pytest.mark.parametrize("pol", [1, 3])
+def test_heun_replicas_full_size(pol):
     from paper_1207_2192_amd import Disk, params_from_si
     n, R, L = 64, 250.0, 20.0
     disk = Disk.batch([R] * n, [L] * n)
-    disk.tune(4, [4] * n, 1)                    # the plan the benchmark runs: 256 workgroups x 768 threads
+    disk.tune(4, [4] * n, pol)                  # the benchmark's plans: 256 workgroups x 768 threads
     assert disk.launch_shape()[:2] == (4, 256)
     D = disk.D[0]
     PY = li.PERMALLOY
@@ -44,11 +45,12 @@ def test_heun_replicas_full_size():
     assert float((nrm - 1).abs().max()) < 1e-6
 
 
-def test_ragged_batch_full_size():
+@pytest.mark.parametrize("pol", [1, 3])
+def test_ragged_batch_full_size(pol):
     from paper_1207_2192_amd import Disk, LLGParams
     ens = li.ragged_ensemble(256)
     disk = Disk.batch([e.R_nm for e in ens], [e.L_nm for e in ens])
-    disk.tune(1, None, 1)                          # one-group workgroups in proportion to the work
+    disk.tune(1, None, pol)                        # one-group workgroups, the library's counts
     m0s = [li.vortex_ansatz(disk.D[k], ens[k].x0_nm / 2.0 + 0.01, ens[k].y0_nm / 2.0) for k in range(disk.n)]
     m = torch.tensor(np.concatenate([x.reshape(-1) for x in m0s]), dtype=torch.float32, device="cuda")
     p = LLGParams(alpha=0.02, c=C_PY, dtau=0.04)

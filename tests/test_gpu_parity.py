@@ -268,24 +268,26 @@ def test_launch_plan_does_not_change_results():
     D = disk.D[0]
     m0 = to_dev(state_in(D, 3, "vortex"))
     p = Prm(alpha=0.05, c=C_PY, dtau=0.04)
-    outs = []
-    for ug, wg in ((1, None), (1, [7]), (2, [5]), (4, [3]), (4, None), (2, [1])):
-        disk.tune(ug, wg, 0)
-        m = m0.clone()
-        disk.rk4_step(m, 6, p)
-        disk.check()
-        outs.append(m)
-    for o in outs[1:]:
-        assert torch.equal(o, outs[0])
+    for pol in (0, 2):                       # both column strategies
+        outs = []
+        for ug, wg in ((1, None), (1, [7]), (2, [5]), (4, [3]), (4, None), (2, [1])):
+            disk.tune(ug, wg, pol)
+            m = m0.clone()
+            disk.rk4_step(m, 6, p)
+            disk.check()
+            outs.append(m)
+        for o in outs[1:]:
+            assert torch.equal(o, outs[0])
 
 
 @pytest.mark.parametrize("R,L,P", [(15.0, 5.0, 0), (30.0, 10.0, 0), (61.0, 12.0, 0), (100.0, 20.0, 0),
                                    (120.0, 10.0, 512)])
-@pytest.mark.parametrize("ug", [1, 4])
-def test_radix8_policy_matches_oracle(R, L, P, ug):
+@pytest.mark.parametrize("ug,pol", [(1, 1), (4, 1), (1, 2), (2, 2), (1, 3), (4, 3)])
+def test_transform_policy_matches_oracle(R, L, P, ug, pol):
+    # radix-8 stages (bit 0) and lane-group columns (bit 1) against the oracle's fields
     Disk, Prm = gpu()
     disk = Disk.build(R, L, 2.0, P)
-    disk.tune(ug, None, 1)
+    disk.tune(ug, None, pol)
     od = oracle.Disk(R, L, 2.0, P=P or None)
     D = disk.D[0]
     m0 = state_in(D, 21 + D)
