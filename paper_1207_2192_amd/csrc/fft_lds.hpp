@@ -129,8 +129,32 @@ constexpr bool fft_whole_radix() {
     return (1 << ((ilog2(P) / ilog2(R)) * ilog2(R))) == P;
 }
 
-template <int P, int R, bool INV, bool KEEP = false, bool WGSYNC = true>
-__device__ __forceinline__ void fft_run(float2 (&v)[R], float2* buf, const float2* tw, int t) {
+// Twiddle powers of the full radix-R stages 1 .. NFULL-1 of one lane: they
+// depend only on the lane's position t in its transform, so a lane that runs
+// many transforms computes them once (w[s-1][j-1] = w_s^j).
+template <int P, int R>
+struct StageTwiddles {
+    static constexpr int NFULL = ilog2(P) / ilog2(R);
+    float2 w[NFULL > 1 ? NFULL - 1 : 1][R - 1];
+};
+template <int P, int R>
+__device__ __forceinline__ void stage_twiddles(StageTwiddles<P, R>& st, const float2* tw, int t) {
+    int Ns = R;
+#pragma unroll
+    for (int s = 1; s < StageTwiddles<P, R>::NFULL; ++s) {
+        float2 w[R];
+        twiddle_powers<R>(tw[(t & (Ns - 1)) * (P / (Ns * R))], w);
+#pragma unroll
+        for (int j = 1; j < R; ++j) st.w[s - 1][j - 1] = w[j];
+        Ns *= R;
+    }
+}
+
+// ZHI: the inputs v[j], j >= R/2 (points at or past P/2) are known to be zero.
+// st: precomputed stage twiddles of this lane (or null: computed per stage).
+template <int P, int R, bool INV, bool KEEP = false, bool WGSYNC = true, bool ZHI = false>
+__device__ __forceinline__ void fft_run(float2 (&v)[R], float2* buf, const float2* tw, int t,
+                                        const StageTwiddles<P, R>* st = nullptr) {
     constexpr int Tf = P / R;
     constexpr int LOGR = ilog2(R);
     constexpr int LOGP = ilog2(P);
@@ -143,11 +167,19 @@ __device__ __forceinline__ void fft_run(float2 (&v)[R], float2* buf, const float
         if (s > 0) {
 #pragma unroll
             for (int j = 0; j < R; ++j) v[j] = buf[pad16(t + j * Tf)];
-            const int kk = t & (Ns - 1);
             float2 w[R];
-            twiddle_powers<R>(tw[kk * (P / (Ns * R))], w);
+            if (st) {
+#pragma unroll
+                for (int j = 1; j < R; ++j) w[j] = st->w[s - 1][j - 1];
+            } else {
+                const int kk = t & (Ns - 1);
+                twiddle_powers<R>(tw[kk * (P / (Ns * R))], w);
+            }
 #pragma unroll
             for (int j = 1; j < R; ++j) v[j] = INV ? cmulc(v[j], w[j]) : cmul(v[j], w[j]);
+        } else if constexpr (ZHI) {
+#pragma unroll
+            for (int j = R / 2; j < R; ++j) v[j] = make_float2(0.f, 0.f);
         }
         dftR<R, INV>(v);
         if (KEEP && s == NFULL - 1) break;

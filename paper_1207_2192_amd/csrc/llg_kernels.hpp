@@ -132,13 +132,13 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
 
     // ---- forward transforms along x of the packed rows in LDS; unpack to S
     auto row_forward_store = [&](int b) {
-        float2 v[R];
+        float2 v[R];   // columns at or past P/2 (>= D) are zero
 #pragma unroll
-        for (int j = 0; j < R; ++j) {
+        for (int j = 0; j < R / 2; ++j) {
             const int i = t + j * Tf;
             v[j] = (i < D) ? mybuf[pad16(i)] : make_float2(0.f, 0.f);
         }
-        fft_run<P, R, false>(v, mybuf, ltw, t);
+        fft_run<P, R, false, false, true, true>(v, mybuf, ltw, t);
         for (int idx = tid<OPQ>(); idx < U * H; idx += NT) {
             int uu, k;
             pair_map(idx, uu, k);
@@ -171,15 +171,18 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     // belongs to its wavefront alone, so the phase has no workgroup barrier;
     // where P is a power of the radix the forward results stay in registers in
     // exactly the order the inverse transform takes them.
+    // Rows at or past P/2 (>= D) are zero on input and not needed on output,
+    // so the points j >= R/2 of a lane are neither loaded nor stored.
     constexpr bool KEEP = fft_whole_radix<P, R>();
     constexpr int NSLOT = 3 * U;
     const int slot = wave * U + u;
+    StageTwiddles<P, R> stw;
     auto col_fwd = [&](float2 (&v)[R]) {
         __builtin_amdgcn_sched_barrier(0);   // one transform at a time: bounds the live registers
         if constexpr (KEEP) {
-            fft_run<P, R, false, true>(v, mybuf, ltw, t);
+            fft_run<P, R, false, true, true, true>(v, mybuf, ltw, t, &stw);
         } else {
-            fft_run<P, R, false, false, false>(v, mybuf, ltw, t);
+            fft_run<P, R, false, false, false, true>(v, mybuf, ltw, t, &stw);
 #pragma unroll
             for (int j = 0; j < R; ++j) v[j] = mybuf[pad16(t + j * Tf)];
             wave_sync();
@@ -188,16 +191,16 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     auto col_inv_store = [&](int c, int kx, bool valid, float2 (&v)[R]) {
         __builtin_amdgcn_sched_barrier(0);
         if constexpr (KEEP) {
-            fft_run<P, R, true, true>(v, mybuf, ltw, t);   // v[j] = column value at row t + j*Tf
+            fft_run<P, R, true, true>(v, mybuf, ltw, t, &stw);   // v[j] = column value at row t + j*Tf
 #pragma unroll
-            for (int j = 0; j < R; ++j) {
+            for (int j = 0; j < R / 2; ++j) {
                 const int i = t + j * Tf;
                 bst2(Srs, (valid && i < D) ? soff(c, kx, i) : OOB, v[j]);
             }
         } else {
-            fft_run<P, R, true, false, false>(v, mybuf, ltw, t);
+            fft_run<P, R, true, false, false>(v, mybuf, ltw, t, &stw);
 #pragma unroll
-            for (int j = 0; j < R; ++j) {
+            for (int j = 0; j < R / 2; ++j) {
                 const int i = t + j * Tf;
                 bst2(Srs, (valid && i < D) ? soff(c, kx, i) : OOB, mybuf[pad16(i)]);
             }
@@ -207,17 +210,18 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     // all column tiles of this workgroup: z first (it needs only Kzz), while the
     // x and y columns are still arriving
     auto column_pass_slot = [&]() {
+        stage_twiddles<P, R>(stw, ltw, t);
         for (int b = g; b < n_cb; b += G) {
             const int kx = b * NSLOT + slot;
             const bool valid = kx < H;
             float2 X[R], Y[R], Z[R];
 #pragma unroll
-            for (int j = 0; j < R; ++j) {
+            for (int j = 0; j < R / 2; ++j) {
                 const int i = t + j * Tf;
                 Z[j] = bld2(Srs, (valid && i < D) ? soff(2, kx, i) : OOB);
             }
 #pragma unroll
-            for (int j = 0; j < R; ++j) {
+            for (int j = 0; j < R / 2; ++j) {
                 const int i = t + j * Tf;
                 const bool ok = valid && i < D;
                 X[j] = bld2(Srs, ok ? soff(0, kx, i) : OOB);
@@ -271,7 +275,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         const int kx = b * U + u;
         const bool valid = kx < H;
 #pragma unroll
-        for (int j = 0; j < R; ++j) {
+        for (int j = 0; j < R / 2; ++j) {   // rows at or past P/2 (>= D) are zero
             const int i = t + j * Tf;
             c.v[j] = bld2(Srs, (valid && i < D) ? soff(wave, kx, i) : OOB);
         }
@@ -294,7 +298,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     auto col_compute = [&](int b, ColV& c, const ColK& kk) {
         const int kx = b * U + u;
         const bool valid = kx < H;
-        fft_run<P, R, false>(c.v, mybuf, ltw, t);   // ends with a workgroup barrier
+        fft_run<P, R, false, false, true, true>(c.v, mybuf, ltw, t);   // ends with a workgroup barrier
         float2 v[R];
 #pragma unroll
         for (int j = 0; j < R; ++j) {
@@ -314,14 +318,14 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         if constexpr (KEEP) {
             fft_run<P, R, true, true>(v, mybuf, ltw, t);   // v[j] = column value at row t + j*Tf
 #pragma unroll
-            for (int j = 0; j < R; ++j) {
+            for (int j = 0; j < R / 2; ++j) {
                 const int i = t + j * Tf;
                 bst2(Srs, (valid && i < D) ? soff(wave, kx, i) : OOB, v[j]);
             }
         } else {
             fft_run<P, R, true>(v, mybuf, ltw, t);
 #pragma unroll
-            for (int j = 0; j < R; ++j) {
+            for (int j = 0; j < R / 2; ++j) {
                 const int i = t + j * Tf;
                 bst2(Srs, (valid && i < D) ? soff(wave, kx, i) : OOB, mybuf[pad16(i)]);
             }
