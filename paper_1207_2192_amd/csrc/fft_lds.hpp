@@ -151,8 +151,10 @@ __device__ __forceinline__ void stage_twiddles(StageTwiddles<P, R>& st, const fl
 }
 
 // ZHI: the inputs v[j], j >= R/2 (points at or past P/2) are known to be zero.
+// ZHO: only the outputs below P/2 are needed; the last stage neither computes
+// nor writes the others (buf keeps stale values there).
 // st: precomputed stage twiddles of this lane (or null: computed per stage).
-template <int P, int R, bool INV, bool KEEP = false, bool WGSYNC = true, bool ZHI = false>
+template <int P, int R, bool INV, bool KEEP = false, bool WGSYNC = true, bool ZHI = false, bool ZHO = false>
 __device__ __forceinline__ void fft_run(float2 (&v)[R], float2* buf, const float2* tw, int t,
                                         const StageTwiddles<P, R>* st = nullptr) {
     constexpr int Tf = P / R;
@@ -185,9 +187,11 @@ __device__ __forceinline__ void fft_run(float2 (&v)[R], float2* buf, const float
         if (KEEP && s == NFULL - 1) break;
         const int kk = t & (Ns - 1);
         const int base = (t - kk) * R + kk;
+        // in the last stage base = t and output j lands at t + j P/R
+        constexpr int NW = (ZHO && REM == 1) ? R / 2 : R;
         wave_sync();
 #pragma unroll
-        for (int j = 0; j < R; ++j) buf[pad16(base + j * Ns)] = v[j];
+        for (int j = 0; j < (s == NFULL - 1 ? NW : R); ++j) buf[pad16(base + j * Ns)] = v[j];
         if (WGSYNC && REM == 1 && s == NFULL - 1)
             __syncthreads();
         else
@@ -217,8 +221,9 @@ __device__ __forceinline__ void fft_run(float2 (&v)[R], float2* buf, const float
             const int k = t + q * Tf;
             const int kk = k & (Ns - 1);
             const int base = (k - kk) * REM + kk;
+            // base = k and output j lands at k + j P/REM in this last stage
 #pragma unroll
-            for (int j = 0; j < REM; ++j) buf[pad16(base + j * Ns)] = u[q * REM + j];
+            for (int j = 0; j < (ZHO ? REM / 2 : REM); ++j) buf[pad16(base + j * Ns)] = u[q * REM + j];
         }
         if constexpr (WGSYNC)
             __syncthreads();

@@ -93,9 +93,14 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
         if (r > 0) {
             k0 += W0;
             k1 += W1;
+            // bumped where used (scalar adds) rather than a precomputed schedule
+            // of twenty long-lived scalar registers
+            asm volatile("" : "+s"(k0), "+s"(k1));
         }
-        const uint32_t hi0 = __umulhi(M0, c0), lo0 = M0 * c0;
-        const uint32_t hi1 = __umulhi(M1, c2), lo1 = M1 * c2;
+        // one 32 x 32 -> 64 multiply per product (a single v_mad_u64_u32)
+        const uint64_t p0 = (uint64_t)M0 * c0, p1 = (uint64_t)M1 * c2;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
         const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
         c1 = lo1;

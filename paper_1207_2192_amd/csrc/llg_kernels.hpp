@@ -198,7 +198,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                 bst2(Srs, (valid && i < D) ? soff(c, kx, i) : OOB, v[j]);
             }
         } else {
-            fft_run<P, R, true, false, false>(v, mybuf, ltw, t, &stw);
+            fft_run<P, R, true, false, false, false, true>(v, mybuf, ltw, t, &stw);
 #pragma unroll
             for (int j = 0; j < R / 2; ++j) {
                 const int i = t + j * Tf;
@@ -323,7 +323,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                 bst2(Srs, (valid && i < D) ? soff(wave, kx, i) : OOB, v[j]);
             }
         } else {
-            fft_run<P, R, true>(v, mybuf, ltw, t);
+            fft_run<P, R, true, false, true, false, true>(v, mybuf, ltw, t);
 #pragma unroll
             for (int j = 0; j < R / 2; ++j) {
                 const int i = t + j * Tf;
@@ -401,7 +401,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         float2 v[R];
 #pragma unroll
         for (int j = 0; j < R; ++j) v[j] = mybuf[pad16(t + j * Tf)];
-        fft_run<P, R, true>(v, mybuf, ltw, t);
+        fft_run<P, R, true, false, true, false, true>(v, mybuf, ltw, t);   // only columns < P/2 (>= D) are read
     };
     auto row_inverse = [&](int b) {
         SRow sv[IS];
@@ -452,6 +452,21 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         float y0[2][3], ac[2][3];
     };
     constexpr int IC = (U * (P / 2) + NT - 1) / NT;   // cell-update items per thread (D <= P/2)
+    // Cell-update item idx -> (row pair uu of the iteration, column i).  Where
+    // the index arithmetic is recomputed inside the loop (OPQ) the columns sit on
+    // a stride of P/2 (shifts, no division by D); where it is hoisted, on a
+    // stride of D (fewer idle items).
+    auto cell_item = [&](int idx, int& uu, int& i) {
+        if constexpr (OPQ) {
+            uu = idx / (P / 2);
+            i = idx % (P / 2);
+            return uu < U && i < D;
+        } else {
+            uu = idx / D;
+            i = idx - uu * D;
+            return idx < U * D;
+        }
+    };
     Gath gv[IC];
     auto gather = [&](int b, int s) {
         const bool need_acc = (mode == MODE_RK4 && s > 0) || (mode == MODE_HEUN && s == 1);
@@ -459,10 +474,10 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         const __amdgpu_buffer_rsrc_t Ars = make_rsrc(d.acc, (unsigned)(3 * DD) * 4u);
 #pragma unroll
         for (int q = 0; q < IC; ++q) {
-            const int idx = tid<OPQ>() + q * NT;
-            const int uu = idx / D, i = idx - uu * D;
+            int uu, i;
+            const bool item = cell_item(tid<OPQ>() + q * NT, uu, i);
             const int p = b * U + uu;
-            const bool live = idx < U * D && p < d.n_pairs;
+            const bool live = item && p < d.n_pairs;
             const int j0 = 2 * p;
             Gath& G_ = gv[q];
 #pragma unroll
@@ -481,9 +496,8 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     auto cell_update = [&](int b, int s, long long n, float* Yn) {
 #pragma unroll
         for (int q = 0; q < IC; ++q) {
-            const int idx = tid<OPQ>() + q * NT;
-            if (idx >= U * D) continue;
-            const int uu = idx / D, i = idx - uu * D;
+            int uu, i;
+            if (!cell_item(tid<OPQ>() + q * NT, uu, i)) continue;   // same items as the gather
             const int p = b * U + uu;
             if (p >= d.n_pairs) continue;
             const int j0 = 2 * p;
