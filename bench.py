@@ -99,7 +99,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(independent disks shard across GPUs without communication; see DESIGN.md)", file=sys.stderr)
+              "(independent disks shard across GPUs without communication)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
