@@ -107,16 +107,17 @@ __device__ __forceinline__ void twiddle_powers(float2 w1, float2 (&w)[R]) {
     }
 }
 
-// LDS layout of a transform buffer: one padding slot after every 16 complex
-// values, so that the strided Stockham writes of a 16-lane group land in 16
-// different bank pairs.
-__device__ __forceinline__ int pad16(int e) { return e + (e >> 4); }
+// LDS layout of a transform buffer: one padding slot after every 8 complex
+// values, so that the strided Stockham writes of every stage (lane strides of
+// 8, 8 R and 1 elements) and the lane-consecutive reads of a 16-lane group land
+// in 16 different bank pairs.
+__device__ __forceinline__ int padb(int e) { return e + (e >> 3); }
 template <int P>
-constexpr int padded_len() { return P + P / 16; }
+constexpr int padded_len() { return P + P / 8; }
 
 // One length-P transform by the lanes t = 0 .. P/R-1 of a lane group.
 // On entry v[j] = x[t + j*(P/R)].  On exit buf holds X in natural order
-// (element e at buf[pad16(e)]).  buf may alias the input storage; tw is the P-entry twiddle table.
+// (element e at buf[padb(e)]).  buf may alias the input storage; tw is the P-entry twiddle table.
 // buf is touched only by the lanes of this transform until the closing
 // workgroup barrier, so every lane of the workgroup must call this the same
 // number of times.
@@ -168,7 +169,7 @@ __device__ __forceinline__ void fft_run(float2 (&v)[R], float2* buf, const float
     for (int s = 0; s < NFULL; ++s) {
         if (s > 0) {
 #pragma unroll
-            for (int j = 0; j < R; ++j) v[j] = buf[pad16(t + j * Tf)];
+            for (int j = 0; j < R; ++j) v[j] = buf[padb(t + j * Tf)];
             float2 w[R];
             if (st) {
 #pragma unroll
@@ -191,7 +192,7 @@ __device__ __forceinline__ void fft_run(float2 (&v)[R], float2* buf, const float
         constexpr int NW = (ZHO && REM == 1) ? R / 2 : R;
         wave_sync();
 #pragma unroll
-        for (int j = 0; j < (s == NFULL - 1 ? NW : R); ++j) buf[pad16(base + j * Ns)] = v[j];
+        for (int j = 0; j < (s == NFULL - 1 ? NW : R); ++j) buf[padb(base + j * Ns)] = v[j];
         if (WGSYNC && REM == 1 && s == NFULL - 1)
             __syncthreads();
         else
@@ -209,7 +210,7 @@ __device__ __forceinline__ void fft_run(float2 (&v)[R], float2* buf, const float
             twiddle_powers<REM>(tw[kk * (P / (Ns * REM))], w);
 #pragma unroll
             for (int j = 0; j < REM; ++j) {
-                float2 x = buf[pad16(k + j * (P / REM))];
+                float2 x = buf[padb(k + j * (P / REM))];
                 if (j > 0) x = INV ? cmulc(x, w[j]) : cmul(x, w[j]);
                 u[q * REM + j] = x;
             }
@@ -223,7 +224,7 @@ __device__ __forceinline__ void fft_run(float2 (&v)[R], float2* buf, const float
             const int base = (k - kk) * REM + kk;
             // base = k and output j lands at k + j P/REM in this last stage
 #pragma unroll
-            for (int j = 0; j < (ZHO ? REM / 2 : REM); ++j) buf[pad16(base + j * Ns)] = u[q * REM + j];
+            for (int j = 0; j < (ZHO ? REM / 2 : REM); ++j) buf[padb(base + j * Ns)] = u[q * REM + j];
         }
         if constexpr (WGSYNC)
             __syncthreads();

@@ -12,7 +12,7 @@ constexpr int WG_THREADS = 192;   // one group of three wavefronts: components x
 constexpr int MAX_UG = 4;         // wavefront groups per workgroup
 constexpr int MAX_P = 512;
 constexpr int MAX_R = 8;
-constexpr int LDS_FFT = 3 * 64 * MAX_R * 17 / 16 + 3 * 4 * 32;   // float2 per group: 3 waves x (64/Tf units) x padded P, bank skew
+constexpr int LDS_FFT = 3 * 64 * MAX_R * 9 / 8 + 3 * 4 * 32;   // float2 per group: 3 waves x (64/Tf units) x padded P, bank skew
 // The row/column spectra are stored in blocks of SB rows: for each spectral
 // column kx the SB values of a block are contiguous (one 64-byte segment), so
 // a column pass reads whole segments and a row pass over SB/2 row pairs

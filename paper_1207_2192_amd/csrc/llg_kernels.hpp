@@ -123,9 +123,9 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                     }
                 }
             }
-            BUF(0, uu)[pad16(i)] = make_float2(x0, y0);
-            BUF(1, uu)[pad16(i)] = make_float2(x1, y1);
-            BUF(2, uu)[pad16(i)] = make_float2(z0, z1);
+            BUF(0, uu)[padb(i)] = make_float2(x0, y0);
+            BUF(1, uu)[padb(i)] = make_float2(x1, y1);
+            BUF(2, uu)[padb(i)] = make_float2(z0, z1);
         }
         __syncthreads();
     };
@@ -136,7 +136,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
 #pragma unroll
         for (int j = 0; j < R / 2; ++j) {
             const int i = t + j * Tf;
-            v[j] = (i < D) ? mybuf[pad16(i)] : make_float2(0.f, 0.f);
+            v[j] = (i < D) ? mybuf[padb(i)] : make_float2(0.f, 0.f);
         }
         fft_run<P, R, false, false, true, true>(v, mybuf, ltw, t);
         for (int idx = tid<OPQ>(); idx < U * H; idx += NT) {
@@ -146,9 +146,9 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             if (p >= d.n_pairs) continue;
             const int j0 = 2 * p;
             const int km = (P - k) & (P - 1);
-            const float2 A0 = BUF(0, uu)[pad16(k)], B0 = BUF(0, uu)[pad16(km)];
-            const float2 A1 = BUF(1, uu)[pad16(k)], B1 = BUF(1, uu)[pad16(km)];
-            const float2 A2 = BUF(2, uu)[pad16(k)], B2 = BUF(2, uu)[pad16(km)];
+            const float2 A0 = BUF(0, uu)[padb(k)], B0 = BUF(0, uu)[padb(km)];
+            const float2 A1 = BUF(1, uu)[padb(k)], B1 = BUF(1, uu)[padb(km)];
+            const float2 A2 = BUF(2, uu)[padb(k)], B2 = BUF(2, uu)[padb(km)];
             // two real rows packed as a + i b:  a^ = (A + conj B)/2,  b^ = (A - conj B)/(2i)
             const float4 sx = make_float4(0.5f * (A0.x + B0.x), 0.5f * (A0.y - B0.y),
                                           0.5f * (A1.x + B1.x), 0.5f * (A1.y - B1.y));
@@ -184,7 +184,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         } else {
             fft_run<P, R, false, false, false, true>(v, mybuf, ltw, t, &stw);
 #pragma unroll
-            for (int j = 0; j < R; ++j) v[j] = mybuf[pad16(t + j * Tf)];
+            for (int j = 0; j < R; ++j) v[j] = mybuf[padb(t + j * Tf)];
             wave_sync();
         }
     };
@@ -202,7 +202,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
 #pragma unroll
             for (int j = 0; j < R / 2; ++j) {
                 const int i = t + j * Tf;
-                bst2(Srs, (valid && i < D) ? soff(c, kx, i) : OOB, mybuf[pad16(i)]);
+                bst2(Srs, (valid && i < D) ? soff(c, kx, i) : OOB, mybuf[padb(i)]);
             }
             wave_sync();
         }
@@ -304,11 +304,11 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         for (int j = 0; j < R; ++j) {
             const int ky = t + j * Tf;
             const float sg = ky <= P / 2 ? 1.f : -1.f;   // K_xy is odd in ky
-            const float2 A = BUF(wave == 2 ? 2 : 0, u)[pad16(ky)];
+            const float2 A = BUF(wave == 2 ? 2 : 0, u)[padb(ky)];
             if (wave == 2) {
                 v[j] = make_float2(kk.k0[j] * A.x, kk.k0[j] * A.y);
             } else {
-                const float2 B = BUF(1, u)[pad16(ky)];
+                const float2 B = BUF(1, u)[padb(ky)];
                 const float ka = wave == 0 ? kk.k0[j] : sg * kk.k0[j];
                 const float kb = wave == 0 ? sg * kk.k1[j] : kk.k1[j];
                 v[j] = make_float2(ka * A.x + kb * B.x, ka * A.y + kb * B.y);
@@ -327,7 +327,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
 #pragma unroll
             for (int j = 0; j < R / 2; ++j) {
                 const int i = t + j * Tf;
-                bst2(Srs, (valid && i < D) ? soff(wave, kx, i) : OOB, mybuf[pad16(i)]);
+                bst2(Srs, (valid && i < D) ? soff(wave, kx, i) : OOB, mybuf[padb(i)]);
             }
         }
     };
@@ -387,20 +387,20 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             pair_map(idx, uu, k);
             const float4 sx = sv[q].x, sy = sv[q].y, sz = sv[q].z;
             // Hx + i Hy of each row, Hz(j0) + i Hz(j1); mirrored half from Hermitian symmetry
-            BUF(0, uu)[pad16(k)] = make_float2(sx.x - sy.y, sx.y + sy.x);
-            BUF(1, uu)[pad16(k)] = make_float2(sx.z - sy.w, sx.w + sy.z);
-            BUF(2, uu)[pad16(k)] = make_float2(sz.x - sz.w, sz.y + sz.z);
+            BUF(0, uu)[padb(k)] = make_float2(sx.x - sy.y, sx.y + sy.x);
+            BUF(1, uu)[padb(k)] = make_float2(sx.z - sy.w, sx.w + sy.z);
+            BUF(2, uu)[padb(k)] = make_float2(sz.x - sz.w, sz.y + sz.z);
             if (k > 0 && k < P / 2) {
                 const int km = P - k;
-                BUF(0, uu)[pad16(km)] = make_float2(sx.x + sy.y, sy.x - sx.y);
-                BUF(1, uu)[pad16(km)] = make_float2(sx.z + sy.w, sy.z - sx.w);
-                BUF(2, uu)[pad16(km)] = make_float2(sz.x + sz.w, sz.z - sz.y);
+                BUF(0, uu)[padb(km)] = make_float2(sx.x + sy.y, sy.x - sx.y);
+                BUF(1, uu)[padb(km)] = make_float2(sx.z + sy.w, sy.z - sx.w);
+                BUF(2, uu)[padb(km)] = make_float2(sz.x + sz.w, sz.z - sz.y);
             }
         }
         __syncthreads();
         float2 v[R];
 #pragma unroll
-        for (int j = 0; j < R; ++j) v[j] = mybuf[pad16(t + j * Tf)];
+        for (int j = 0; j < R; ++j) v[j] = mybuf[padb(t + j * Tf)];
         fft_run<P, R, true, false, true, false, true>(v, mybuf, ltw, t);   // only columns < P/2 (>= D) are read
     };
     auto row_inverse = [&](int b) {
@@ -515,7 +515,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             }
             const float (&y0)[2][3] = gv[q].y0;
             const float (&ac)[2][3] = gv[q].ac;
-            const float2 hz2 = BUF(2, uu)[pad16(i)];
+            const float2 hz2 = BUF(2, uu)[padb(i)];
             float nxt[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
             float3 wn[2];
             if (mode == MODE_HEUN && (in_disk(j0, i, D) || (j0 + 1 < D && in_disk(j0 + 1, i, D))))
@@ -527,7 +527,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                 if (j >= D) break;
                 const int cell = j * D + i;
                 const bool in = in_disk(j, i, D);
-                const float2 hxy = BUF(r, uu)[pad16(i)];
+                const float2 hxy = BUF(r, uu)[padb(i)];
                 const float Hx = hxy.x, Hy = hxy.y, Hz = r == 0 ? hz2.x : hz2.y;
                 if (mode == MODE_DEMAG) {
                     gbl(out)[cell] = in ? Hx : 0.f;
@@ -645,9 +645,9 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                 nxt[r][2] = nzv;
             }
             if (mode == MODE_RK4 || mode == MODE_HEUN) {
-                BUF(0, uu)[pad16(i)] = make_float2(nxt[0][0], nxt[0][1]);
-                BUF(1, uu)[pad16(i)] = make_float2(nxt[1][0], nxt[1][1]);
-                BUF(2, uu)[pad16(i)] = make_float2(nxt[0][2], nxt[1][2]);
+                BUF(0, uu)[padb(i)] = make_float2(nxt[0][0], nxt[0][1]);
+                BUF(1, uu)[padb(i)] = make_float2(nxt[1][0], nxt[1][1]);
+                BUF(2, uu)[padb(i)] = make_float2(nxt[0][2], nxt[1][2]);
             }
         }
         __syncthreads();
@@ -710,7 +710,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                     yb0[r][c] = (sta && okc) ? ld_sh(m + cell) : 0.f;
                 }
             }
-            const float2 hz2 = BUF(2, uu)[pad16(i)];
+            const float2 hz2 = BUF(2, uu)[padb(i)];
             float nxt[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
@@ -728,7 +728,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                 float yprev[3] = {0.f, 0.f, 0.f};
                 float ybar[3] = {yb0[r][0], yb0[r][1], yb0[r][2]};
                 if (fin) {
-                    const float2 kxy = BUF(r, uu)[pad16(i)];
+                    const float2 kxy = BUF(r, uu)[padb(i)];
                     const float Kb[3] = {kxy.x, kxy.y, r == 0 ? hz2.x : hz2.y};
                     float accn[3];
 #pragma unroll
@@ -792,9 +792,9 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                 }
             }
             if (sta) {
-                BUF(0, uu)[pad16(i)] = make_float2(nxt[0][0], nxt[0][1]);
-                BUF(1, uu)[pad16(i)] = make_float2(nxt[1][0], nxt[1][1]);
-                BUF(2, uu)[pad16(i)] = make_float2(nxt[0][2], nxt[1][2]);
+                BUF(0, uu)[padb(i)] = make_float2(nxt[0][0], nxt[0][1]);
+                BUF(1, uu)[padb(i)] = make_float2(nxt[1][0], nxt[1][1]);
+                BUF(2, uu)[padb(i)] = make_float2(nxt[0][2], nxt[1][2]);
             }
         }
         __syncthreads();
@@ -836,7 +836,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             if (sta && sg != 0.f && (in_disk(j0, i, D) || (j0 + 1 < D && in_disk(j0 + 1, i, D))))
                 thermal_normals_pair(a.seed, step0 + (unsigned long long)ns, (unsigned long long)(p * D + i),
                                      (unsigned long long)(a.replica0 + d.k), wn[0], wn[1]);
-            const float2 hz2 = BUF(2, uu)[pad16(i)];
+            const float2 hz2 = BUF(2, uu)[padb(i)];
             float nxt[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
@@ -856,7 +856,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                 // ---- finish the stage whose gbar field is in LDS (Kb) and in Bf (exchange)
                 float fin_tot[3] = {0.f, 0.f, 0.f};
                 if (fin) {
-                    const float2 kxy = BUF(r, uu)[pad16(i)];
+                    const float2 kxy = BUF(r, uu)[padb(i)];
                     const float Kb[3] = {kxy.x, kxy.y, r == 0 ? hz2.x : hz2.y};
                     const float hh[3] = {hxf, hyf, hzf};
 #pragma unroll
@@ -955,9 +955,9 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                 nxt[r][2] = bz;
             }
             if (sta) {
-                BUF(0, uu)[pad16(i)] = make_float2(nxt[0][0], nxt[0][1]);
-                BUF(1, uu)[pad16(i)] = make_float2(nxt[1][0], nxt[1][1]);
-                BUF(2, uu)[pad16(i)] = make_float2(nxt[0][2], nxt[1][2]);
+                BUF(0, uu)[padb(i)] = make_float2(nxt[0][0], nxt[0][1]);
+                BUF(1, uu)[padb(i)] = make_float2(nxt[1][0], nxt[1][1]);
+                BUF(2, uu)[padb(i)] = make_float2(nxt[0][2], nxt[1][2]);
             }
         }
         __syncthreads();
@@ -996,7 +996,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                     rgt[r][c] = okr ? ld_sh(cur + cell + 1) : 0.f;
                 }
             }
-            const float2 hz2 = BUF(2, uu)[pad16(i)];
+            const float2 hz2 = BUF(2, uu)[padb(i)];
             float nxt_v[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
@@ -1004,7 +1004,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                 if (j >= D) break;
                 const int cell = j * D + i;
                 if (in_disk(j, i, D)) {
-                    const float2 hxy = BUF(r, uu)[pad16(i)];
+                    const float2 hxy = BUF(r, uu)[padb(i)];
                     const float Hz = r == 0 ? hz2.x : hz2.y;
                     const float mx = col[r + 1][0], my = col[r + 1][1], mz = col[r + 1][2];
                     double dx = ((double)i - half) - Xc, dy = ((double)j - half) - Yc;
@@ -1037,9 +1037,9 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                 st_sh(nxt + DD + cell, nxt_v[r][1]);
                 st_sh(nxt + 2 * DD + cell, nxt_v[r][2]);
             }
-            BUF(0, uu)[pad16(i)] = make_float2(nxt_v[0][0], nxt_v[0][1]);
-            BUF(1, uu)[pad16(i)] = make_float2(nxt_v[1][0], nxt_v[1][1]);
-            BUF(2, uu)[pad16(i)] = make_float2(nxt_v[0][2], nxt_v[1][2]);
+            BUF(0, uu)[padb(i)] = make_float2(nxt_v[0][0], nxt_v[0][1]);
+            BUF(1, uu)[padb(i)] = make_float2(nxt_v[1][0], nxt_v[1][1]);
+            BUF(2, uu)[padb(i)] = make_float2(nxt_v[0][2], nxt_v[1][2]);
         }
         __syncthreads();
     };
