@@ -411,14 +411,33 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
 
     // ---- stage state rows 2bU-1 .. 2bU+2U of iteration b into LDS (masked; zero
     // outside the box), halo[(c*HR + rr)*HW + 1 + i] for row 2bU-1+rr and column i
+    // Staged-row element q of this thread.  Where the index arithmetic is
+    // recomputed inside the loop (OPQ) the rows are spread over the wavefronts,
+    // one whole row per wavefront and round (row = wave + r * waves, uniform
+    // across the wavefront) with lane l taking columns l + 64 v (coalesced), so
+    // the per-element arithmetic is an add and the disk test; where it is
+    // hoisted, elements run over rows x columns by thread index.
     constexpr int HC = P / 2;                    // staged columns (D <= P/2)
-    constexpr int IH = (3 * HR * HC + NT - 1) / NT;
+    constexpr int NWV = 3 * UG;                  // wavefronts of the workgroup
+    constexpr int VW = HC >= 64 ? HC / 64 : 1;   // columns per lane and row
+    constexpr int HQ = (3 * HR + NWV - 1) / NWV; // rounds of rows
+    constexpr int IH = OPQ ? HQ * VW : (3 * HR * HC + NT - 1) / NT;
+    auto halo_elem = [&](int q, int& row, int& i) {
+        if constexpr (OPQ) {
+            row = __builtin_amdgcn_readfirstlane(tid<OPQ>() >> 6) + (q / VW) * NWV;
+            i = (tid<OPQ>() & 63) + 64 * (q % VW);
+        } else {
+            const int e = tid<OPQ>() + q * NT;
+            row = e / HC;
+            i = e % HC;
+        }
+    };
     auto halo_load = [&](int b, const float* Ys, float (&hv)[IH]) {
         const __amdgpu_buffer_rsrc_t Yr = make_rsrc(Ys, (unsigned)(3 * DD) * 4u);
 #pragma unroll
         for (int q = 0; q < IH; ++q) {
-            const int e = tid<OPQ>() + q * NT;
-            const int row = e / HC, i = e % HC;
+            int row, i;
+            halo_elem(q, row, i);
             const int c = row / HR, rr = row - c * HR;
             const int j = 2 * b * U - 1 + rr;
             const bool ok = row < 3 * HR && i < D && j >= 0 && j < D && in_disk(j, i, D);
@@ -428,9 +447,9 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     auto halo_store = [&](const float (&hv)[IH]) {
 #pragma unroll
         for (int q = 0; q < IH; ++q) {
-            const int e = tid<OPQ>() + q * NT;
-            const int row = e / HC, i = e % HC;
-            if (row < 3 * HR) halo[row * HW + 1 + i] = hv[q];
+            int row, i;
+            halo_elem(q, row, i);
+            if (row < 3 * HR && i < HC) halo[row * HW + 1 + i] = hv[q];
         }
     };
 
