@@ -12,6 +12,9 @@
   Delta(m) = m x [g - alpha (m x g)], the predictor is m~ = m + Delta(m) and the
   corrector m' = m + (Delta(m) + Delta~(m~))/2, where Delta~ uses b(m~) and the
   same noise vector w.
+* A time-dependent external field enters b at each stage's own time: RK4 at
+  tau_n, tau_n + dtau/2 (twice) and tau_n + dtau, Heun at tau_n (predictor)
+  and tau_n + dtau (corrector), with tau_n = tau0 + n dtau.
 
 Reading for the renormalisation, on which the paper is silent: when
 ``Params.renorm`` is set, |m| is reset to 1 after every full step (never at
@@ -41,16 +44,17 @@ def exchange_field(m: torch.Tensor, disk: Disk) -> torch.Tensor:
     return disk.apply_mask(b)
 
 
-def _hext(prm: Params, like: torch.Tensor) -> torch.Tensor:
-    h = torch.tensor(prm.hext, dtype=like.dtype)
+def _hext(prm: Params, like: torch.Tensor, tau: float | None) -> torch.Tensor:
+    h = torch.tensor(prm.field_at(prm.tau0 if tau is None else tau), dtype=like.dtype)
     return h.view(3, 1, 1)
 
 
-def effective_field(m: torch.Tensor, disk: Disk, prm: Params, H: torch.Tensor | None = None) -> torch.Tensor:
-    """b = b_ex + c (h_ext + H^M) (eq. Bi)."""
+def effective_field(m: torch.Tensor, disk: Disk, prm: Params, H: torch.Tensor | None = None,
+                    tau: float | None = None) -> torch.Tensor:
+    """b = b_ex + c (h_ext(tau) + H^M) (eq. Bi); tau = None means prm.tau0."""
     if H is None:
         H = demag_fft(m, disk)
-    b = exchange_field(m, disk) + prm.c * (_hext(prm, m) + H)
+    b = exchange_field(m, disk) + prm.c * (_hext(prm, m, tau) + H)
     return disk.apply_mask(b)
 
 
@@ -60,10 +64,10 @@ def torque(m: torch.Tensor, b: torch.Tensor, alpha: float) -> torch.Tensor:
     return mxb - alpha * torch.linalg.cross(m, mxb, dim=-3)
 
 
-def llg_rhs(m: torch.Tensor, disk: Disk, prm: Params) -> torch.Tensor:
-    """dm/dtau at state m."""
+def llg_rhs(m: torch.Tensor, disk: Disk, prm: Params, tau: float | None = None) -> torch.Tensor:
+    """dm/dtau at state m and time tau (None: prm.tau0)."""
     mm = disk.apply_mask(m)
-    return disk.apply_mask(torque(mm, effective_field(mm, disk, prm), prm.alpha))
+    return disk.apply_mask(torque(mm, effective_field(mm, disk, prm, tau=tau), prm.alpha))
 
 
 def normalise(m: torch.Tensor, disk: Disk) -> torch.Tensor:
@@ -75,28 +79,32 @@ def normalise(m: torch.Tensor, disk: Disk) -> torch.Tensor:
 def rk4_step(m: torch.Tensor, disk: Disk, prm: Params, nsteps: int = 1) -> torch.Tensor:
     y = disk.apply_mask(m.to(torch.float64))
     h = prm.dtau
-    for _ in range(nsteps):
-        k1 = llg_rhs(y, disk, prm)
-        k2 = llg_rhs(y + 0.5 * h * k1, disk, prm)
-        k3 = llg_rhs(y + 0.5 * h * k2, disk, prm)
-        k4 = llg_rhs(y + h * k3, disk, prm)
+    for n in range(nsteps):
+        t = prm.tau0 + n * float(h)          # the field is taken at each stage's own time
+        k1 = llg_rhs(y, disk, prm, t)
+        k2 = llg_rhs(y + 0.5 * h * k1, disk, prm, t + 0.5 * float(h))
+        k3 = llg_rhs(y + 0.5 * h * k2, disk, prm, t + 0.5 * float(h))
+        k4 = llg_rhs(y + h * k3, disk, prm, t + float(h))
         y = y + (h / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
         if prm.renorm:
             y = normalise(y, disk)
     return y
 
 
-def heun_update(m: torch.Tensor, disk: Disk, prm: Params, w: torch.Tensor) -> torch.Tensor:
-    """One H2 step from m with the noise vector w (same shape as m)."""
+def heun_update(m: torch.Tensor, disk: Disk, prm: Params, w: torch.Tensor, tau: float | None = None) -> torch.Tensor:
+    """One H2 step from m at time tau (None: prm.tau0) with the noise vector w
+    (same shape as m); the predictor's field is taken at tau, the corrector's at
+    tau + dtau."""
     sig = prm.sigma()
+    t0 = prm.tau0 if tau is None else tau
 
-    def delta(x):
-        g = effective_field(x, disk, prm) * prm.dtau + sig * w
+    def delta(x, t):
+        g = effective_field(x, disk, prm, tau=t) * prm.dtau + sig * w
         return disk.apply_mask(torque(x, g, prm.alpha))
 
-    d1 = delta(m)
+    d1 = delta(m, t0)
     mt = m + d1
-    d2 = delta(mt)
+    d2 = delta(mt, t0 + float(prm.dtau))
     out = m + 0.5 * (d1 + d2)
     return normalise(out, disk) if prm.renorm else disk.apply_mask(out)
 
@@ -107,7 +115,7 @@ def heun_step(m: torch.Tensor, disk: Disk, prm: Params, *, seed: int, step0: int
     y = disk.apply_mask(m.to(torch.float64))
     for n in range(nsteps):
         w = torch.from_numpy(gaussian_field(seed, step0 + n, replica, disk.D))
-        y = heun_update(y, disk, prm, w)
+        y = heun_update(y, disk, prm, w, prm.tau0 + n * float(prm.dtau))
     return y
 
 
@@ -118,5 +126,5 @@ def heun_step_replicas(m: torch.Tensor, disk: Disk, prm: Params, *, seed: int, s
     reps = list(replicas)
     for n in range(nsteps):
         w = torch.from_numpy(gaussian_field(seed, step0 + n, np.asarray(reps), disk.D))
-        y = heun_update(y, disk, prm, w)
+        y = heun_update(y, disk, prm, w, prm.tau0 + n * float(prm.dtau))
     return y

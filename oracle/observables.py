@@ -42,7 +42,7 @@ def energy(m: torch.Tensor, disk: Disk, prm: Params):
     e_ex = -(dot_h[hb].sum() + dot_v[vb].sum())
     H = demag_fft(mm, disk)
     e_dm = -0.5 * prm.c * (H * mm).sum()
-    h = torch.tensor(prm.hext, dtype=torch.float64).view(3, 1, 1)
+    h = torch.tensor(prm.field_at(prm.tau0), dtype=torch.float64).view(3, 1, 1)
     e_ext = -prm.c * (h * mm).sum()
     e = e_ex + e_dm + e_ext
     return float(e), float(e_ex), float(e_dm), float(e_ext)
@@ -52,7 +52,7 @@ def energy_from_exchange_field(m: torch.Tensor, disk: Disk, prm: Params) -> floa
     """Same total energy written with b_ex: -(1/2) sum m.b_ex - c sum (h + H/2).m."""
     mm = disk.apply_mask(m.to(torch.float64))
     H = demag_fft(mm, disk)
-    h = torch.tensor(prm.hext, dtype=torch.float64).view(3, 1, 1)
+    h = torch.tensor(prm.field_at(prm.tau0), dtype=torch.float64).view(3, 1, 1)
     return float(-0.5 * (mm * exchange_field(mm, disk)).sum() - prm.c * ((h + 0.5 * H) * mm).sum())
 
 

@@ -35,6 +35,12 @@ class Params:
     renorm    renormalise |m| = 1 after every full step.
     fd_factor divide the noise variance by (1 + alpha^2) (off = the paper's
               sigma^2 = 2 alpha T dtau).
+
+    Time-dependent external field (the h_ext of eq. Hmm and eq. Bi as a function
+    of time, a reading: the paper keeps it constant):
+      h_ext(tau) = hext + hac sin(2 pi freq tau + phase)
+                        + hpulse exp(-(tau - tpulse)^2 / (2 wpulse^2)),
+    tau0 = the time at the first step of an integration call.
     """
     alpha: float = 0.0
     c: float = 0.0
@@ -43,6 +49,20 @@ class Params:
     dtau: float = 0.04
     renorm: bool = False
     fd_factor: bool = False
+    hac: tuple = (0.0, 0.0, 0.0)
+    freq: float = 0.0
+    phase: float = 0.0
+    hpulse: tuple = (0.0, 0.0, 0.0)
+    tpulse: float = 0.0
+    wpulse: float = 1.0
+    tau0: float = 0.0
+
+    def field_at(self, tau: float) -> tuple:
+        """h_ext at time tau (3 floats)."""
+        osc = math.sin(2.0 * math.pi * self.freq * tau + self.phase)
+        pulse = math.exp(-((tau - self.tpulse) ** 2) / (2.0 * self.wpulse ** 2)) if any(self.hpulse) else 0.0
+        return tuple(float(self.hext[i]) + float(self.hac[i]) * osc + float(self.hpulse[i]) * pulse
+                     for i in range(3))
 
     def sigma(self) -> float:
         """Standard deviation of one noise component per step,
