@@ -59,12 +59,24 @@ typedef struct llg_disk_s* llg_disk;
 /* Dimensionless parameters of one disk (Sec. II.A, Sec. III).
  *   alpha     Gilbert damping.
  *   c         a^2/lambda_ex^2; multiplies the demag and external fields in b (eq. Bi).
- *   hext      external field / Ms.
+ *   hext      external field / Ms (its constant part).
  *   temp      scaled temperature kT/(2AL) (Sec. III.B).
  *   dtau      time step in units of t0.
  *   renorm    nonzero: reset |m| = 1 after every full step.
  *   fd_factor nonzero: noise variance 2 alpha T dtau / (1 + alpha^2) instead of
- *             the paper's 2 alpha T dtau (Sec. III.C). */
+ *             the paper's 2 alpha T dtau (Sec. III.C).
+ * Time-dependent driving field (the h_ext of eq. Hmm and eq. Bi as a function of
+ * time; all zero = a constant field):
+ *   h_ext(tau) = hext + hac sin(2 pi freq tau + phase)
+ *                     + hpulse exp(-(tau - tpulse)^2 / (2 wpulse^2))
+ *   hac, freq, phase  oscillating part: amplitude / Ms, cycles per unit of tau, radians;
+ *   hpulse, tpulse, wpulse  Gaussian pulse: amplitude / Ms, centre and width in tau
+ *             (wpulse > 0 whenever hpulse is nonzero);
+ *   tau0      the time at the start of the call.  Step n of a call runs from
+ *             tau0 + n dtau; RK4 evaluates the field at its stage times (fractions
+ *             0, 1/2, 1/2, 1 of the step), Heun at the start (predictor) and the
+ *             end (corrector) of the step; llg_demag_field, llg_rhs, llg_energy and
+ *             llg_relax use h_ext(tau0). */
 typedef struct {
     double alpha;
     double c;
@@ -73,6 +85,13 @@ typedef struct {
     double dtau;
     int renorm;
     int fd_factor;
+    double hac[3];
+    double freq;
+    double phase;
+    double hpulse[3];
+    double tpulse;
+    double wpulse;
+    double tau0;
 } llg_params;
 
 /* Fill *out (host) from SI material data: exchange stiffness A (J/m), Ms (A/m),
@@ -161,6 +180,32 @@ int llg_rk4_step(llg_disk h, float* m, long long nsteps, const llg_params* p, vo
 int llg_heun_step(llg_disk h, float* m, long long nsteps, unsigned long long seed,
                   unsigned long long step0, unsigned int replica, const llg_params* p,
                   void* stream);
+
+/* The integrators with an observable series (float64, on the device): like
+ * llg_rk4_step / llg_heun_step, and in addition, for every step n of the call
+ * with n mod sample_every = 0, the state at the start of that step gives
+ * series[((n / sample_every) * n_disks + k) * 4 + q] = (<m_x>, <m_y>, <m_z>, E)
+ * of disk k (Sec. IV: spatial average over the disk cells; eq. Hmm: the energy
+ * in units of J at the field of that instant).  series (device) needs
+ * ceil(nsteps / sample_every) * n_disks * 4 doubles; sample_every >= 1.  The
+ * sums are reduced in a fixed order (deterministic).  These sequences are the
+ * input of the power spectra of Sec. V.B (llg_power_spectrum). */
+int llg_rk4_series(llg_disk h, float* m, long long nsteps, const llg_params* p, long long sample_every,
+                   double* series, void* stream);
+int llg_heun_series(llg_disk h, float* m, long long nsteps, unsigned long long seed, unsigned long long step0,
+                    unsigned int replica, const llg_params* p, long long sample_every, double* series,
+                    void* stream);
+
+/* Power spectra of real float64 sequences (Sec. V.B: spectra of <m_x>(tau)).
+ * Sequence b (0 <= b < n_seq) has elements x_b[t] = x[b * bstride + t * tstride],
+ * t = 0 .. len-1 (device array).  With remove_mean set the sequence's mean is
+ * subtracted; window 0 = none, 1 = Hann, w[t] = sin^2(pi t / len).  Then
+ * X_b[k] = sum_t w[t] x_b[t] exp(-2 pi i t k / len) and
+ * out[b * (len/2 + 1) + k] = |X_b[k]|^2 / len for k = 0 .. len/2 (device).
+ * len must be a power of two in [16, 2^24].  work (device) holds 4 * len * n_seq
+ * doubles.  float64 radix-2 Stockham passes through work. */
+int llg_power_spectrum(const double* x, int n_seq, long long bstride, long long len, long long tstride,
+                       int remove_mean, int window, double* work, double* out, void* stream);
 
 /* step0 value for llg_heun_step: take the first step index from the handle's
  * device-side step counter and advance the counter by nsteps afterwards (in

@@ -15,7 +15,9 @@ P_int = ctypes.POINTER(ctypes.c_int)
 
 class LLGParamsC(ctypes.Structure):
     _fields_ = [("alpha", c_double), ("c", c_double), ("hext", c_double * 3), ("temp", c_double),
-                ("dtau", c_double), ("renorm", c_int), ("fd_factor", c_int)]
+                ("dtau", c_double), ("renorm", c_int), ("fd_factor", c_int),
+                ("hac", c_double * 3), ("freq", c_double), ("phase", c_double),
+                ("hpulse", c_double * 3), ("tpulse", c_double), ("wpulse", c_double), ("tau0", c_double)]
 
 
 # name -> (restype, argtypes)
@@ -38,6 +40,10 @@ SIGNATURES = {
     "llg_rhs": (c_int, [c_vp, c_vp, c_vp, ctypes.POINTER(LLGParamsC), c_vp]),
     "llg_rk4_step": (c_int, [c_vp, c_vp, c_ll, ctypes.POINTER(LLGParamsC), c_vp]),
     "llg_heun_step": (c_int, [c_vp, c_vp, c_ll, c_ull, c_ull, c_uint, ctypes.POINTER(LLGParamsC), c_vp]),
+    "llg_rk4_series": (c_int, [c_vp, c_vp, c_ll, ctypes.POINTER(LLGParamsC), c_ll, c_vp, c_vp]),
+    "llg_heun_series": (c_int, [c_vp, c_vp, c_ll, c_ull, c_ull, c_uint, ctypes.POINTER(LLGParamsC), c_ll, c_vp,
+                                c_vp]),
+    "llg_power_spectrum": (c_int, [c_vp, c_int, c_ll, c_ll, c_ll, c_int, c_int, c_vp, c_vp, c_vp]),
     "llg_step_counter_set": (c_int, [c_vp, c_ull, c_vp]),
     "llg_step_counter_get": (c_int, [c_vp, ctypes.POINTER(c_ull), c_vp]),
     "llg_graph_create": (c_int, [c_vp, c_int, c_vp, c_ll, ctypes.POINTER(LLGParamsC), c_ull, c_uint,

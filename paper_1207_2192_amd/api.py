@@ -18,7 +18,9 @@ from ._lib import LLGParamsC, check
 
 @dataclass
 class LLGParams:
-    """Dimensionless parameters (see llg_params in include/llgdisk.h)."""
+    """Dimensionless parameters (see llg_params in include/llgdisk.h), including the
+    time-dependent field h_ext(tau) = hext + hac sin(2 pi freq tau + phase)
+    + hpulse exp(-(tau - tpulse)^2 / (2 wpulse^2)) and the start time tau0."""
     alpha: float = 0.0
     c: float = 0.0
     hext: tuple = (0.0, 0.0, 0.0)
@@ -26,13 +28,24 @@ class LLGParams:
     dtau: float = 0.04
     renorm: bool = False
     fd_factor: bool = False
+    hac: tuple = (0.0, 0.0, 0.0)
+    freq: float = 0.0
+    phase: float = 0.0
+    hpulse: tuple = (0.0, 0.0, 0.0)
+    tpulse: float = 0.0
+    wpulse: float = 1.0
+    tau0: float = 0.0
 
     def to_c(self) -> LLGParamsC:
         p = LLGParamsC()
         p.alpha, p.c, p.temp, p.dtau = self.alpha, self.c, self.temp, self.dtau
         for i in range(3):
             p.hext[i] = float(self.hext[i])
+            p.hac[i] = float(self.hac[i])
+            p.hpulse[i] = float(self.hpulse[i])
         p.renorm, p.fd_factor = int(bool(self.renorm)), int(bool(self.fd_factor))
+        p.freq, p.phase, p.tpulse, p.wpulse, p.tau0 = (float(self.freq), float(self.phase), float(self.tpulse),
+                                                       float(self.wpulse), float(self.tau0))
         return p
 
 
@@ -184,6 +197,30 @@ class Disk:
                                         self._params(params), _stream()), "llg_heun_step")
         return m
 
+    def rk4_series(self, m: torch.Tensor, nsteps: int, params, sample_every: int) -> torch.Tensor:
+        """RK4 steps in place with the observable series (llg_rk4_series): returns
+        [ceil(nsteps / sample_every), n, 4] float64 (<m_x>, <m_y>, <m_z>, E) of the state
+        at the start of every sample_every-th step."""
+        m = self._state(m)
+        ns = -(-int(nsteps) // int(sample_every))
+        out = torch.empty(max(ns, 1), self.n, 4, dtype=torch.float64, device=self.device)
+        check(_lib.load().llg_rk4_series(self._h, _ptr(m), int(nsteps), self._params(params), int(sample_every),
+                                         _ptr(out), _stream()), "llg_rk4_series")
+        return out[:ns]
+
+    def heun_series(self, m: torch.Tensor, nsteps: int, params, sample_every: int, *, seed: int, step0=0,
+                    replica: int = 0) -> torch.Tensor:
+        """Heun steps in place with the observable series (llg_heun_series); step0=None
+        continues the handle's step counter."""
+        m = self._state(m)
+        ns = -(-int(nsteps) // int(sample_every))
+        out = torch.empty(max(ns, 1), self.n, 4, dtype=torch.float64, device=self.device)
+        s0 = _lib.STEP_COUNTER if step0 is None else int(step0)
+        check(_lib.load().llg_heun_series(self._h, _ptr(m), int(nsteps), int(seed), s0, int(replica),
+                                          self._params(params), int(sample_every), _ptr(out), _stream()),
+              "llg_heun_series")
+        return out[:ns]
+
     def set_step(self, step: int):
         check(_lib.load().llg_step_counter_set(self._h, int(step), _stream()), "llg_step_counter_set")
 
@@ -317,6 +354,21 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+def power_spectrum(x: torch.Tensor, remove_mean: bool = True, window: str = "none") -> torch.Tensor:
+    """llg_power_spectrum of the rows of x ([n_seq, len] or [len], float64 on the GPU,
+    len a power of two): |X_k|^2 / len for k = 0 .. len/2."""
+    if x.dtype != torch.float64 or x.device.type != "cuda":
+        raise TypeError("x must be a float64 CUDA tensor")
+    x2 = x.reshape(-1, x.shape[-1])
+    n_seq, n = x2.shape
+    out = torch.empty(n_seq, n // 2 + 1, dtype=torch.float64, device=x.device)
+    work = torch.empty(4 * n * n_seq, dtype=torch.float64, device=x.device)
+    check(_lib.load().llg_power_spectrum(_ptr(x2), int(n_seq), int(x2.stride(0)), int(n), int(x2.stride(1)),
+                                         int(bool(remove_mean)), {"none": 0, "hann": 1}[window], _ptr(work),
+                                         _ptr(out), _stream()), "llg_power_spectrum")
+    return out.reshape(*x.shape[:-1], n // 2 + 1)
 
 
 def build_kernels(R_nm: float, L_nm: float, a_nm: float = 2.0, P: int = 0) -> Disk:

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = ["llgdisk.hip", "kernels_field.hip", "kernels_rk4.hip", "kernels_heun.hip", "kernels_vjp.hip",
-           "kernels_heun_vjp.hip", "kernels_relax.hip"]
+           "kernels_heun_vjp.hip", "kernels_relax.hip", "kernels_rk4_series.hip", "kernels_heun_series.hip"]
 OUT = os.path.join(HERE, "libllgdisk.so")
 
 HIPCC_FLAGS = [

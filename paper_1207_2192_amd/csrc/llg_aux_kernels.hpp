@@ -269,4 +269,70 @@ __global__ __launch_bounds__(OBS_THREADS) void core_vjp_kernel(const DiskDesc* d
     }
 }
 
+// ---------------------------------------------------------------- power spectra
+// Periodogram of real float64 sequences: mean, window, radix-2 Stockham passes
+// in float64 through global memory (one launch per pass), |X_k|^2 / len.
+// Sequence b is x[b * bstride + t * tstride]; block y = sequence.
+
+// Mean of each sequence (or 0) into slot [b * len].x of buffer M.
+__global__ __launch_bounds__(256) void ps_mean(const double* x, long long bstride, long long len,
+                                               long long tstride, int remove_mean, double2* M) {
+    __shared__ double sh[4];
+    const int b = blockIdx.x;
+    const double* xb = x + (long long)b * bstride;
+    double s = 0.0;
+    if (remove_mean)
+        for (long long t = threadIdx.x; t < len; t += 256) s += xb[t * tstride];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) M[(long long)b * len] = make_double2((sh[0] + sh[1] + sh[2] + sh[3]) / (double)len, 0.0);
+}
+
+// A[b][t] = w[t] (x_b[t] - mean_b) as complex numbers; w = 1 or the Hann window sin^2(pi t / len).
+__global__ __launch_bounds__(256) void ps_load(const double* x, long long bstride, long long len, long long tstride,
+                                               int window, const double2* M, double2* A) {
+    const int b = blockIdx.y;
+    const double mean = M[(long long)b * len].x;
+    const double* xb = x + (long long)b * bstride;
+    for (long long t = blockIdx.x * 256ll + threadIdx.x; t < len; t += (long long)gridDim.x * 256) {
+        double v = xb[t * tstride] - mean;
+        if (window == 1) {
+            const double sn = sinpi((double)t / (double)len);
+            v *= sn * sn;
+        }
+        A[(long long)b * len + t] = make_double2(v, 0.0);
+    }
+}
+
+// One radix-2 Stockham pass (sub-transforms of length Ns -> 2 Ns): for
+// t < len/2, a = in[t], c = in[t + len/2] W^kk with kk = t mod Ns and
+// W = exp(-i pi / Ns); out[2 (t - kk) + kk] = a + c, out[2 (t - kk) + kk + Ns] = a - c.
+__global__ __launch_bounds__(256) void ps_pass(const double2* in, double2* out, long long len, long long Ns) {
+    const int b = blockIdx.y;
+    const double2* ib = in + (long long)b * len;
+    double2* ob = out + (long long)b * len;
+    const long long half = len / 2;
+    for (long long t = blockIdx.x * 256ll + threadIdx.x; t < half; t += (long long)gridDim.x * 256) {
+        const long long kk = t & (Ns - 1);
+        const double2 a = ib[t], c0 = ib[t + half];
+        double sw, cw;
+        sincospi(-(double)kk / (double)Ns, &sw, &cw);
+        const double2 c = make_double2(c0.x * cw - c0.y * sw, c0.x * sw + c0.y * cw);
+        const long long base = 2 * (t - kk) + kk;
+        ob[base] = make_double2(a.x + c.x, a.y + c.y);
+        ob[base + Ns] = make_double2(a.x - c.x, a.y - c.y);
+    }
+}
+
+// out[b * (len/2 + 1) + k] = |X_b[k]|^2 / len, k = 0 .. len/2.
+__global__ __launch_bounds__(256) void ps_power(const double2* X, long long len, double* out) {
+    const int b = blockIdx.y;
+    const long long nk = len / 2 + 1;
+    for (long long k = blockIdx.x * 256ll + threadIdx.x; k < nk; k += (long long)gridDim.x * 256) {
+        const double2 v = X[(long long)b * len + k];
+        out[(long long)b * nk + k] = (v.x * v.x + v.y * v.y) / (double)len;
+    }
+}
+
 }  // namespace llg

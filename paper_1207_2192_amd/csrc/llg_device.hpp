@@ -41,8 +41,59 @@ struct DiskPrm {
     float alpha, c, hx, hy, hz, dtau, sigma;
     float dsigma;          // d sigma / d alpha (Heun adjoint)
     int renorm;
+    int drive;             // nonzero: h_ext has a time-dependent part
     double c_d, hx_d, hy_d, hz_d;
+    double dtau_d, tau0;   // time step and the time at the start of the call
+    double hac[3], freq, phase;      // h_ac sin(2 pi freq tau + phase)
+    double hpulse[3], tpulse, inv2w2;   // h_pulse exp(-(tau - tpulse)^2 inv2w2), inv2w2 = 1/(2 w^2)
+    float hacf[3], hpulsef[3];       // the same amplitudes in float32 (integrator kernels)
+    float phase_rev;                 // phase / (2 pi), reduced to [0, 1)
+    float inv2w2_log2e;              // inv2w2 / ln 2 (exponent for exp2)
 };
+
+// External field at time tau (the h_ext of eq. Hmm and eq. Bi, here allowed to
+// depend on time): the constant part, an oscillation and a Gaussian pulse.
+// float64; the oscillation's phase is reduced to one period before the sine.
+struct Field3 {
+    double x, y, z;
+};
+__device__ __forceinline__ Field3 hext_at(const DiskPrm& pr, double tau) {
+    Field3 h{pr.hx_d, pr.hy_d, pr.hz_d};
+    if (pr.drive) {
+        double fr = pr.freq * tau;
+        fr -= floor(fr);
+        const double sn = sin(6.283185307179586476925286766559 * fr + pr.phase);
+        const double u = tau - pr.tpulse;
+        const double gs = pr.inv2w2 > 0.0 ? exp(-u * u * pr.inv2w2) : 0.0;
+        h.x += pr.hac[0] * sn + pr.hpulse[0] * gs;
+        h.y += pr.hac[1] * sn + pr.hpulse[1] * gs;
+        h.z += pr.hac[2] * sn + pr.hpulse[2] * gs;
+    }
+    return h;
+}
+
+// The same field in float32 for the integrator kernels, where a float64 sine
+// and exponential would raise the register count of the whole persistent
+// kernel: the oscillation's phase is reduced to one period in float64, then
+// the hardware sine of an angle in revolutions and the hardware exp2 (a few
+// ulp each; the field enters the float32 induction anyway).
+__device__ __forceinline__ void hext_at_f(const DiskPrm& pr, double tau, float& hx, float& hy, float& hz) {
+    hx = pr.hx;
+    hy = pr.hy;
+    hz = pr.hz;
+    if (pr.drive) {
+        double fr = pr.freq * tau;
+        fr -= floor(fr);
+        float rv = (float)fr + pr.phase_rev;
+        rv -= rv >= 1.0f ? 1.0f : 0.0f;
+        const float sn = __builtin_amdgcn_sinf(rv);
+        const float u = (float)(tau - pr.tpulse);
+        const float gs = pr.inv2w2_log2e > 0.f ? __builtin_amdgcn_exp2f(-u * u * pr.inv2w2_log2e) : 0.f;
+        hx += pr.hacf[0] * sn + pr.hpulsef[0] * gs;
+        hy += pr.hacf[1] * sn + pr.hpulsef[1] * gs;
+        hz += pr.hacf[2] * sn + pr.hpulsef[2] * gs;
+    }
+}
 
 enum Mode : int {
     MODE_DEMAG = 0,
@@ -78,6 +129,11 @@ struct KArgs {
     double* relax_out;      // per disk: lambda_x, lambda_y, sweeps, residual, C_x, C_y, 0, 0
     double kappa, tol;
     double relax_cut2;      // squared constraint radius around the target (units of a^2); <= 0: whole disk
+    // observable series of the integrators: every `every` steps (0 = none) the
+    // state at the start of the step gives series[(sample * n_disks + k) * 4 + q] =
+    // (<m_x>, <m_y>, <m_z>, E) in float64
+    double* series;
+    int every, n_disks;
 };
 
 // ---------------------------------------------------------------- Philox4x32-10

@@ -42,7 +42,7 @@ struct RowTile {
     static constexpr int floats = 3 * HR * HW;
 };
 
-template <int P, int R, int UG, int MODE, bool LARGE, bool SLOT>
+template <int P, int R, int UG, int MODE, bool LARGE, bool SLOT, bool SER>
 __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, const DiskPrm& pr, int g,
                                          float2* lds, float2* ltw, float* halo) {
     constexpr int Tf = P / R;
@@ -454,7 +454,39 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     };
 
     double e_ex = 0.0, e_dm = 0.0, e_ext = 0.0;
-    const float hxf = pr.hx, hyf = pr.hy, hzf = pr.hz, cf = pr.c, al = pr.alpha, dt = pr.dtau;
+    const float cf = pr.c, al = pr.alpha, dt = pr.dtau;
+    // external field of the stage being evaluated: constant, or set per stage
+    // from its time when h_ext depends on time
+    float hxf = pr.hx, hyf = pr.hy, hzf = pr.hz;
+    double hxd = pr.hx_d, hyd = pr.hy_d, hzd = pr.hz_d;
+    // (float64 for the field kernel's energy and the relaxation, both at tau0;
+    // float32 hardware transcendentals in the integrators' stage loop)
+    auto set_field = [&](double tau) {
+        if (pr.drive) {
+            if constexpr (MODE == MODE_RK4 || MODE == MODE_HEUN) {
+                hext_at_f(pr, tau, hxf, hyf, hzf);
+                hxd = hxf;
+                hyd = hyf;
+                hzd = hzf;
+            } else {
+                const Field3 h = hext_at(pr, tau);
+                hxd = h.x;
+                hyd = h.y;
+                hzd = h.z;
+                hxf = (float)h.x;
+                hyf = (float)h.y;
+                hzf = (float)h.z;
+            }
+        }
+    };
+    set_field(pr.tau0);
+    // stage times as fractions of a step: RK4 (0, 1/2, 1/2, 1), Heun (0, 1)
+    auto stage_frac = [](int nst, int s) { return nst == 4 ? (s == 0 ? 0.0 : s == 3 ? 1.0 : 0.5) : (double)s; };
+    // observable series (kernel instances with SER only): per-thread float64
+    // sums of m and of the energy density of the state at the start of a
+    // sampled step (its field is the stage-0 field)
+    constexpr bool SERIES = SER && (MODE == MODE_RK4 || MODE == MODE_HEUN);
+    double sm[4] = {0.0, 0.0, 0.0, 0.0};
 
     // ---- per-cell work after the inverse transforms; new stage state back into LDS
     // stage s of step n; Ys = state whose field is in LDS; Yn = where the next stage state goes.
@@ -513,6 +545,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         }
     };
     auto cell_update = [&](int b, int s, long long n, float* Yn) {
+        const bool sample = SERIES && s == 0 && n % a.every == 0;
 #pragma unroll
         for (int q = 0; q < IC; ++q) {
             int uu, i;
@@ -564,12 +597,26 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                     const double mxd = mx, myd = my, mzd = mz;
                     e_ex += -0.5 * (mxd * e3[0] + myd * e3[1] + mzd * e3[2]);
                     e_dm += -0.5 * pr.c_d * (mxd * (double)Hx + myd * (double)Hy + mzd * (double)Hz);
-                    e_ext += -pr.c_d * (mxd * pr.hx_d + myd * pr.hy_d + mzd * pr.hz_d);
+                    e_ext += -pr.c_d * (mxd * hxd + myd * hyd + mzd * hzd);
                     continue;
                 }
                 const float bx = (col[r][0] + col[r + 2][0] + lft[r][0] + rgt[r][0]) + cf * (hxf + Hx);
                 const float by = (col[r][1] + col[r + 2][1] + lft[r][1] + rgt[r][1]) + cf * (hyf + Hy);
                 const float bz = (col[r][2] + col[r + 2][2] + lft[r][2] + rgt[r][2]) + cf * (hzf + Hz);
+                if (sample && in) {
+                    // m and the energy density -1/2 m.b_ex - c (h + H/2).m of the step's start state
+                    const double mxd = mx, myd = my, mzd = mz;
+                    double e3[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        e3[c] = (double)col[r][c] + (double)col[r + 2][c] + (double)lft[r][c] + (double)rgt[r][c];
+                    sm[0] += mxd;
+                    sm[1] += myd;
+                    sm[2] += mzd;
+                    sm[3] += -0.5 * (mxd * e3[0] + myd * e3[1] + mzd * e3[2]) -
+                             pr.c_d * (mxd * (hxd + 0.5 * (double)Hx) + myd * (hyd + 0.5 * (double)Hy) +
+                                       mzd * (hzd + 0.5 * (double)Hz));
+                }
                 float nx = 0.f, ny = 0.f, nzv = 0.f;
                 if (mode == MODE_RHS || mode == MODE_RK4) {
                     // f = m x b - alpha m x (m x b)
@@ -692,6 +739,11 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         const GLOBAL_AS float* Yrec = gbl(recd) + ((size_t)(ns * 4 + ss) * 2) * 3 * DD;
         const GLOBAL_AS float* Hrec = Yrec + 3 * DD;
         const GLOBAL_AS float* Hfin = gbl(recd) + ((size_t)(nf * 4 + sf) * 2 + 1) * 3 * DD;
+        // external field at the finishing and at the starting stage
+        const Field3 hF = hext_at(pr, pr.tau0 + ((double)nf + stage_frac(4, sf)) * pr.dtau_d);
+        const Field3 hS = hext_at(pr, pr.tau0 + ((double)ns + stage_frac(4, ss)) * pr.dtau_d);
+        const float hh[3] = {(float)hF.x, (float)hF.y, (float)hF.z};
+        const float hsx = (float)hS.x, hsy = (float)hS.y, hsz = (float)hS.z;
         for (int idx = tid<OPQ>(); idx < U * D; idx += NT) {
             const int uu = idx / D, i = idx - uu * D;
             const int p = b * U + uu;
@@ -756,7 +808,6 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                         yprev[c] = ax[r][c] + ex + cf * Kb[c];
                         accn[c] = ac[r][c] + yprev[c];
                     }
-                    const float hh[3] = {hxf, hyf, hzf};
 #pragma unroll
                     for (int c = 0; c < 3; ++c) e_dm += (double)bc[r + 1][c] * ((double)hh[c] + (double)hf[r][c]);
                     if (sf == 0) {  // step nf complete: yb_nf = accumulated cotangent
@@ -781,9 +832,9 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                     const float ky = w * ybar[1] + v * yprev[1];
                     const float kz = w * ybar[2] + v * yprev[2];
                     const float Yx = yc[r + 1][0], Yy = yc[r + 1][1], Yz = yc[r + 1][2];
-                    const float bx = (yc[r][0] + yc[r + 2][0] + yl[r][0] + yr[r][0]) + cf * (hxf + hs[r][0]);
-                    const float by = (yc[r][1] + yc[r + 2][1] + yl[r][1] + yr[r][1]) + cf * (hyf + hs[r][1]);
-                    const float bz = (yc[r][2] + yc[r + 2][2] + yl[r][2] + yr[r][2]) + cf * (hzf + hs[r][2]);
+                    const float bx = (yc[r][0] + yc[r + 2][0] + yl[r][0] + yr[r][0]) + cf * (hsx + hs[r][0]);
+                    const float by = (yc[r][1] + yc[r + 2][1] + yl[r][1] + yr[r][1]) + cf * (hsy + hs[r][1]);
+                    const float bz = (yc[r][2] + yc[r + 2][2] + yl[r][2] + yr[r][2]) + cf * (hsz + hs[r][2]);
                     // Y x b
                     const float px = Yy * bz - Yz * by, py = Yz * bx - Yx * bz, pz = Yx * by - Yy * bx;
                     // kb x Y
@@ -846,6 +897,10 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         const GLOBAL_AS float* Y0rec = gbl(recd) + ((size_t)(ns * 2) * 2) * 3 * DD;      // m_ns (stage 1 state)
         const GLOBAL_AS float* Hfin = gbl(recd) + ((size_t)(nf * 2 + sf) * 2 + 1) * 3 * DD;
         const float sg = pr.sigma, dsg = pr.dsigma;
+        const Field3 hF = hext_at(pr, pr.tau0 + ((double)nf + (double)sf) * pr.dtau_d);
+        const Field3 hS = hext_at(pr, pr.tau0 + ((double)ns + (double)ss) * pr.dtau_d);
+        const float hh[3] = {(float)hF.x, (float)hF.y, (float)hF.z};
+        const float hsv[3] = {(float)hS.x, (float)hS.y, (float)hS.z};
         for (int idx = tid<OPQ>(); idx < U * D; idx += NT) {
             const int uu = idx / D, i = idx - uu * D;
             const int p = b * U + uu;
@@ -877,7 +932,6 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                 if (fin) {
                     const float2 kxy = BUF(r, uu)[padb(i)];
                     const float Kb[3] = {kxy.x, kxy.y, r == 0 ? hz2.x : hz2.y};
-                    const float hh[3] = {hxf, hyf, hzf};
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
                         const int o = c * DD + cell;
@@ -906,7 +960,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                     Yv[c] = Yrec[o];
                     const float ex = (oku ? Yrec[o - D] : 0.f) + (okd ? Yrec[o + D] : 0.f) +
                                      (okl ? Yrec[o - 1] : 0.f) + (okr ? Yrec[o + 1] : 0.f);
-                    bv[c] = ex + cf * ((c == 0 ? hxf : c == 1 ? hyf : hzf) + Hrec[o]);
+                    bv[c] = ex + cf * (hsv[c] + Hrec[o]);
                 }
                 const float w3[3] = {r == 0 ? wn[0].x : wn[1].x, r == 0 ? wn[0].y : wn[1].y,
                                      r == 0 ? wn[0].z : wn[1].z};
@@ -1240,6 +1294,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                 for (int s = 0; s < nst; ++s) {
                     column_pass();
                     if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
+                    set_field(pr.tau0 + ((double)n + stage_frac(nst, s)) * pr.dtau_d);
                     const bool last = (n == a.nsteps - 1) && (s == nst - 1);
                     // state whose field is evaluated (Ys) and where the next stage state goes (Yn)
                     const float* Ys;
@@ -1252,7 +1307,33 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                         Yn = (s == 0) ? d.ya : m;
                     }
                     row_pass(s, n, Ys, Yn, !last);
+                    const bool sampled = SERIES && s == 0 && n % a.every == 0;
+                    if (sampled) {   // this workgroup's sums of the sample into its partial slots 4..7
+                        __shared__ double red4[3 * MAX_UG][4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const double v = wave_sum(sm[q]);
+                            if (lane == 0) red4[wv][q] = v;
+                            sm[q] = 0.0;
+                        }
+                        __syncthreads();
+                        if (tid<OPQ>() < 4) {
+                            const int q = tid<OPQ>();
+                            double acc = 0.0;
+                            for (int w = 0; w < 3 * UG; ++w) acc += red4[w][q];
+                            st_shd(d.part + g * PART_STRIDE + 4 + q, acc);
+                        }
+                    }
                     if (!last && !group_barrier(d.bar, ++epoch * G, G, a.err)) return;
+                    // stage 0 is never the last stage: every workgroup's partials of a
+                    // sample are visible here; workgroup 0 sums them in workgroup order
+                    if (sampled && g == 0 && tid<OPQ>() < 4) {
+                        const int q = tid<OPQ>();
+                        double acc = 0.0;
+                        for (int gg = 0; gg < G; ++gg) acc += ld_shd(d.part + gg * PART_STRIDE + 4 + q);
+                        const long long smp = n / a.every;
+                        gbl(a.series)[(smp * a.n_disks + d.k) * 4 + q] = q < 3 ? acc / (double)d.n_cells : acc;
+                    }
                 }
             }
         }
@@ -1275,9 +1356,9 @@ constexpr bool column_slots(int POL, int MODE) {
 }
 
 // One persistent kernel per (workgroup shape UG, transform policy POL, mode,
-// largest FFT size PMAX of the handle): each instance carries only the code
-// and registers of its own path.  MODE_DEMAG stands for the field kernel
-// (demag, rhs and energy, chosen at run time).
+// largest FFT size PMAX of the handle, observable series SER): each instance
+// carries only the code and registers of its own path.  MODE_DEMAG stands for
+// the field kernel (demag, rhs and energy, chosen at run time).
 template <int UG, int POL>
 constexpr int halo_floats(int PMAX) {
     int n = RowTile<64, Radix<64, POL>::value, UG>::floats;
@@ -1292,7 +1373,7 @@ constexpr int halo_floats(int PMAX) {
 // budget the compiler must meet); the other modes take what they need.
 constexpr int min_waves_per_simd(int mode) { return (mode == MODE_RK4 || mode == MODE_HEUN) ? 3 : 1; }
 
-template <int UG, int POL, int MODE, int PMAX>
+template <int UG, int POL, int MODE, int PMAX, bool SER>
 __global__ __launch_bounds__(WG_THREADS* UG) __attribute__((amdgpu_waves_per_eu(min_waves_per_simd(MODE))))
 void llg_persistent(KArgs a) {
     __shared__ float2 lds[LDS_FFT * UG];
@@ -1306,11 +1387,11 @@ void llg_persistent(KArgs a) {
     const DiskPrm pr = a.prm[di];
     constexpr bool L = PMAX >= 512, SL = column_slots(POL, MODE);
     switch (d.P) {
-        case 64: run_disk<64, Radix<64, POL>::value, UG, MODE, L, SL>(a, d, pr, g, lds, ltw, halo); break;
-        case 128: run_disk<128, Radix<128, POL>::value, UG, MODE, L, SL>(a, d, pr, g, lds, ltw, halo); break;
-        case 256: run_disk<256, Radix<256, POL>::value, UG, MODE, L, SL>(a, d, pr, g, lds, ltw, halo); break;
+        case 64: run_disk<64, Radix<64, POL>::value, UG, MODE, L, SL, SER>(a, d, pr, g, lds, ltw, halo); break;
+        case 128: run_disk<128, Radix<128, POL>::value, UG, MODE, L, SL, SER>(a, d, pr, g, lds, ltw, halo); break;
+        case 256: run_disk<256, Radix<256, POL>::value, UG, MODE, L, SL, SER>(a, d, pr, g, lds, ltw, halo); break;
         case 512:
-            if constexpr (PMAX >= 512) run_disk<512, Radix<512, POL>::value, UG, MODE, L, SL>(a, d, pr, g, lds, ltw, halo);
+            if constexpr (PMAX >= 512) run_disk<512, Radix<512, POL>::value, UG, MODE, L, SL, SER>(a, d, pr, g, lds, ltw, halo);
             break;
         default: break;
     }
@@ -1318,11 +1399,11 @@ void llg_persistent(KArgs a) {
 
 // Kernel pointer of the instance for (UG, POL, PMAX) of one mode; modes without
 // the lane-group column strategy share the instances of policies 0 and 1.
-template <int MODE>
+template <int MODE, bool SER = false>
 const void* persistent_instance(int UG, int POL, int PMAX) {
 #define LLG_INST(ug, pl, pm)                                   \
     if (UG == ug && POL == pl && PMAX == pm)                   \
-        return reinterpret_cast<const void*>(llg_persistent<ug, pl, MODE, pm>);
+        return reinterpret_cast<const void*>(llg_persistent<ug, pl, MODE, pm, SER>);
     if (!column_slots(POL, MODE)) POL &= 1;
     LLG_INST(1, 0, 256) LLG_INST(2, 0, 256) LLG_INST(4, 0, 256)
     LLG_INST(1, 1, 256) LLG_INST(2, 1, 256) LLG_INST(4, 1, 256)

@@ -29,6 +29,8 @@ const void* persistent_kernel_heun(int UG, int RSEL, int PMAX);
 const void* persistent_kernel_vjp(int UG, int RSEL, int PMAX);
 const void* persistent_kernel_heun_vjp(int UG, int RSEL, int PMAX);
 const void* persistent_kernel_relax(int UG, int RSEL, int PMAX);
+const void* persistent_kernel_rk4_series(int UG, int RSEL, int PMAX);
+const void* persistent_kernel_heun_series(int UG, int RSEL, int PMAX);
 }  // namespace llg
 
 using namespace llg;
@@ -207,22 +209,36 @@ struct llg_disk_s {
 };
 
 // An executable graph of one persistent launch (barrier reset, integrator,
-// step-counter advance) with its own copy of the parameters.
+// step-counter advance) with its own copies of the parameters and of the
+// launch plan (workgroup maps, descriptors with their partial-sum buffers), so
+// that a later re-plan of the handle leaves the graph's launch intact.
 struct llg_graph_s {
     llg_disk h = nullptr;
-    DiskPrm* prm = nullptr;
+    std::vector<void*> allocs;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     ~llg_graph_s() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
-        if (prm) (void)hipFree(prm);
+        for (void* p : allocs) (void)hipFree(p);
+    }
+    template <typename T>
+    hipError_t dalloc(T** p, size_t count) {
+        void* q = nullptr;
+        hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+        if (e == hipSuccess) {
+            allocs.push_back(q);
+            *p = static_cast<T*>(q);
+        }
+        return e;
     }
 };
 
 namespace {
 
-const void* persistent_kernel(int mode, int UG, int RSEL, int PMAX) {
+const void* persistent_kernel(int mode, int UG, int RSEL, int PMAX, bool series = false) {
+    if (series) return mode == MODE_HEUN ? persistent_kernel_heun_series(UG, RSEL, PMAX)
+                                         : persistent_kernel_rk4_series(UG, RSEL, PMAX);
     switch (mode) {
         case MODE_RK4: return persistent_kernel_rk4(UG, RSEL, PMAX);
         case MODE_HEUN: return persistent_kernel_heun(UG, RSEL, PMAX);
@@ -440,11 +456,9 @@ int create(int n, const double* R_nm, const double* L_nm, double a_nm, const int
     *out = nullptr;
     if (n <= 0 || !R_nm || !L_nm) return fail(LLG_EINVAL, "need n >= 1 disks");
     if (!(a_nm > 0)) return fail(LLG_EINVAL, "cell edge must be positive");
-    auto h = new llg_disk_s();
-    auto bail = [&](int rc) {
-        delete h;
-        return rc;
-    };
+    // owned until the end: every early return (HIP_TRY included) frees the partial handle
+    std::unique_ptr<llg_disk_s> owner(new llg_disk_s());
+    llg_disk h = owner.get();
     HIP_TRY(hipGetDevice(&h->device));
     h->n = n;
     h->a_nm = a_nm;
@@ -453,11 +467,11 @@ int create(int n, const double* R_nm, const double* L_nm, double a_nm, const int
         const double dd = 2.0 * R_nm[k] / a_nm;
         const int D = (int)std::lround(dd);
         if (!(std::fabs(dd - D) <= 1e-9) || D < 1)
-            return bail(fail(LLG_EINVAL, "disk " + std::to_string(k) + ": 2R/a is not a positive integer"));
-        if (!(L_nm[k] > 0)) return bail(fail(LLG_EINVAL, "disk " + std::to_string(k) + ": thickness must be positive"));
+            return fail(LLG_EINVAL, "disk " + std::to_string(k) + ": 2R/a is not a positive integer");
+        if (!(L_nm[k] > 0)) return fail(LLG_EINVAL, "disk " + std::to_string(k) + ": thickness must be positive");
         int P = 0;
         int rc = choose_P(D, P_override ? P_override[k] : 0, &P);
-        if (rc) return bail(rc);
+        if (rc) return rc;
         const double ell = L_nm[k] / a_nm;
         const auto key = std::make_tuple(D, P, (long long)std::llround(ell * 1e12));
         auto it = geom_index.find(key);
@@ -469,8 +483,8 @@ int create(int n, const double* R_nm, const double* L_nm, double a_nm, const int
             g.ell = ell;
             std::vector<unsigned char> mk = disk_mask(D, &g.n_cells);
             std::vector<float> sp = kernel_spectra(D, P, ell);
-            if ((rc = h->dalloc(&g.mask, mk.size()))) return bail(rc);
-            if ((rc = h->dalloc(&g.spec, sp.size()))) return bail(rc);
+            if ((rc = h->dalloc(&g.mask, mk.size()))) return rc;
+            if ((rc = h->dalloc(&g.spec, sp.size()))) return rc;
             HIP_TRY(hipMemcpy(g.mask, mk.data(), mk.size(), hipMemcpyHostToDevice));
             HIP_TRY(hipMemcpy(g.spec, sp.data(), sp.size() * sizeof(float), hipMemcpyHostToDevice));
             gi = (int)h->geoms.size();
@@ -484,7 +498,7 @@ int create(int n, const double* R_nm, const double* L_nm, double a_nm, const int
             for (int e = 0; e < P; ++e)
                 tw[e] = make_float2((float)std::cos(2.0 * M_PI * e / P), (float)(-std::sin(2.0 * M_PI * e / P)));
             float2* tdev = nullptr;
-            if ((rc = h->dalloc(&tdev, P))) return bail(rc);
+            if ((rc = h->dalloc(&tdev, P))) return rc;
             HIP_TRY(hipMemcpy(tdev, tw.data(), P * sizeof(float2), hipMemcpyHostToDevice));
             h->twiddles[P] = tdev;
         }
@@ -502,10 +516,10 @@ int create(int n, const double* R_nm, const double* L_nm, double a_nm, const int
     // ---- per-disk workspaces
     int rc = 0;
     h->n_bars = n * 32;  // one 128-byte line per disk
-    if ((rc = h->dalloc(&h->bars, h->n_bars))) return bail(rc);
-    if ((rc = h->dalloc(&h->err_dev, 1))) return bail(rc);
+    if ((rc = h->dalloc(&h->bars, h->n_bars))) return rc;
+    if ((rc = h->dalloc(&h->err_dev, 1))) return rc;
     HIP_TRY(hipMemset(h->err_dev, 0, sizeof(int)));
-    if ((rc = h->dalloc(&h->step_dev, 1))) return bail(rc);
+    if ((rc = h->dalloc(&h->step_dev, 1))) return rc;
     HIP_TRY(hipMemset(h->step_dev, 0, sizeof(unsigned long long)));
     h->desc.assign(n, DiskDesc{});
     for (int k = 0; k < n; ++k) {
@@ -520,20 +534,20 @@ int create(int n, const double* R_nm, const double* L_nm, double a_nm, const int
         d.k = k;
         d.m_off = h->m_off[k];
         const size_t DD = (size_t)d.D * d.D;
-        if ((rc = h->dalloc(&d.ya, 3 * DD))) return bail(rc);
-        if ((rc = h->dalloc(&d.yb, 3 * DD))) return bail(rc);
-        if ((rc = h->dalloc(&d.acc, 3 * DD))) return bail(rc);
-        if ((rc = h->dalloc(&d.aux, 3 * DD))) return bail(rc);
-        if ((rc = h->dalloc(&d.S, (size_t)3 * d.H * d.Dp))) return bail(rc);
+        if ((rc = h->dalloc(&d.ya, 3 * DD))) return rc;
+        if ((rc = h->dalloc(&d.yb, 3 * DD))) return rc;
+        if ((rc = h->dalloc(&d.acc, 3 * DD))) return rc;
+        if ((rc = h->dalloc(&d.aux, 3 * DD))) return rc;
+        if ((rc = h->dalloc(&d.S, (size_t)3 * d.H * d.Dp))) return rc;
         HIP_TRY(hipMemset(d.S, 0, (size_t)3 * d.H * d.Dp * sizeof(float2)));
         d.spec = g.spec;
         d.mask = g.mask;
         d.tw = h->twiddles[d.P];
         d.bar = h->bars + 32 * k;
     }
-    if ((rc = plan(h, default_unit_groups(h), 0, wg_per_disk))) return bail(rc);
-    if ((rc = h->dalloc(&h->prm_dev, n))) return bail(rc);
-    if ((rc = h->dalloc(&h->hint_dev, 2 * (size_t)n))) return bail(rc);
+    if ((rc = plan(h, default_unit_groups(h), 0, wg_per_disk))) return rc;
+    if ((rc = h->dalloc(&h->prm_dev, n))) return rc;
+    if ((rc = h->dalloc(&h->hint_dev, 2 * (size_t)n))) return rc;
     HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->prm_pin), n * sizeof(DiskPrm), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->hint_pin), 2 * n * sizeof(double), hipHostMallocDefault));
     HIP_TRY(hipEventCreateWithFlags(&h->prm_event, hipEventDisableTiming));
@@ -542,17 +556,27 @@ int create(int n, const double* R_nm, const double* L_nm, double a_nm, const int
     HIP_TRY(hipEventRecord(h->hint_event, 0));
     h->prm_cache.resize(n);
     HIP_TRY(hipDeviceSynchronize());
-    *out = h;
+    *out = owner.release();
     return 0;
 }
 
 int upload_params(llg_disk h, const llg_params* p, hipStream_t st) {
     if (!p) return fail(LLG_EINVAL, "null params");
     std::vector<DiskPrm> v(h->n);
+    std::memset(static_cast<void*>(v.data()), 0, v.size() * sizeof(DiskPrm));   // padding compares equal
     for (int k = 0; k < h->n; ++k) {
         const llg_params& q = p[k];
         if (!(q.dtau >= 0) || !(q.alpha >= 0) || !(q.temp >= 0) || !std::isfinite(q.c))
             return fail(LLG_EINVAL, "invalid parameters for disk " + std::to_string(k));
+        const bool pulse = q.hpulse[0] != 0.0 || q.hpulse[1] != 0.0 || q.hpulse[2] != 0.0;
+        const bool osc = q.hac[0] != 0.0 || q.hac[1] != 0.0 || q.hac[2] != 0.0;
+        bool finite = std::isfinite(q.freq) && std::isfinite(q.phase) && std::isfinite(q.tpulse) &&
+                      std::isfinite(q.wpulse) && std::isfinite(q.tau0);
+        for (int c = 0; c < 3; ++c) finite = finite && std::isfinite(q.hac[c]) && std::isfinite(q.hpulse[c]) &&
+                                             std::isfinite(q.hext[c]);
+        if (!finite || (pulse && !(q.wpulse > 0)))
+            return fail(LLG_EINVAL, "invalid driving field for disk " + std::to_string(k) +
+                                        " (non-finite value, or a pulse without a positive width)");
         DiskPrm& d = v[k];
         d.alpha = (float)q.alpha;
         d.c = (float)q.c;
@@ -574,6 +598,25 @@ int upload_params(llg_disk h, const llg_params* p, hipStream_t st) {
         d.hx_d = q.hext[0];
         d.hy_d = q.hext[1];
         d.hz_d = q.hext[2];
+        d.dtau_d = q.dtau;
+        d.tau0 = q.tau0;
+        d.drive = (osc || pulse) ? 1 : 0;
+        for (int c = 0; c < 3; ++c) {
+            d.hac[c] = osc ? q.hac[c] : 0.0;
+            d.hpulse[c] = pulse ? q.hpulse[c] : 0.0;
+        }
+        d.freq = q.freq;
+        d.phase = q.phase;
+        d.tpulse = q.tpulse;
+        d.inv2w2 = pulse ? 1.0 / (2.0 * q.wpulse * q.wpulse) : 0.0;
+        for (int c = 0; c < 3; ++c) {
+            d.hacf[c] = (float)d.hac[c];
+            d.hpulsef[c] = (float)d.hpulse[c];
+        }
+        const double prv = q.phase / (2.0 * M_PI);
+        d.phase_rev = (float)(prv - std::floor(prv));
+        if (d.phase_rev >= 1.0f) d.phase_rev = 0.0f;
+        d.inv2w2_log2e = (float)(d.inv2w2 / std::log(2.0));
     }
     if (h->prm_valid && std::memcmp(v.data(), h->prm_cache.data(), v.size() * sizeof(DiskPrm)) == 0) return 0;
     HIP_TRY(hipEventSynchronize(h->prm_event));  // the staging buffer is free again
@@ -609,13 +652,17 @@ KArgs make_args(llg_disk h, const DiskPrm* prm, int mode, float* m, float* out, 
     a.replica0 = replica0;
     a.mode = mode;
     a.err = h->err_dev;
+    a.series = nullptr;
+    a.every = 0;
+    a.n_disks = h->n;
     return a;
 }
 
 int launch(llg_disk h, int mode, float* m, float* out, long long nsteps, unsigned long long seed,
            unsigned long long step0, unsigned int replica0, hipStream_t st, float* rec = nullptr,
            const double* relax_x = nullptr, double* relax_out = nullptr, double kappa = 0.0, double tol = 0.0,
-           const unsigned long long* step_ptr = nullptr, double relax_cut2 = 0.0) {
+           const unsigned long long* step_ptr = nullptr, double relax_cut2 = 0.0,
+           double* series = nullptr, long long every = 0) {
     const int kmode = (mode == MODE_RHS || mode == MODE_ENERGY) ? MODE_DEMAG : mode;   // kernel of the mode
     if (!(h->plan_modes & (1u << kmode))) {
         int cap = 0;
@@ -626,14 +673,28 @@ int launch(llg_disk h, int mode, float* m, float* out, long long nsteps, unsigne
                                               " workgroups, tuned for the integrator) exceeds what this mode keeps "
                                               "co-resident (" + std::to_string(cap) + "); re-plan with llg_tune");
     }
+    if (series) {   // the series instance of the integrator: check its own co-residency
+        const void* k = persistent_kernel(mode, h->UG, h->RSEL, h->PMAX, true);
+        if (!k) return fail(LLG_EUNSUPPORTED, "no series kernel instance for this launch shape");
+        int dev = 0, ncu = 0, b = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k, WG_THREADS * h->UG, 0));
+        if (h->n_wg > ncu * b)
+            return fail(LLG_EUNSUPPORTED, "the launch plan (" + std::to_string(h->n_wg) +
+                                              " workgroups) exceeds what the series kernel keeps co-resident (" +
+                                              std::to_string(ncu * b) + "); re-plan with llg_tune");
+    }
     const int nb = (h->n_bars + 255) / 256;
     hipLaunchKernelGGL(zero_u32, dim3(nb), dim3(256), 0, st, h->bars, h->n_bars);
     HIP_TRY(hipGetLastError());
     KArgs a = make_args(h, h->prm_dev, mode, m, out, nsteps, seed, step0, replica0, step_ptr, rec, relax_x,
                         relax_out, kappa, tol, relax_cut2);
+    a.series = series;
+    a.every = (int)every;
     void* args[] = {&a};
-    HIP_TRY(hipLaunchCooperativeKernel(persistent_kernel(mode, h->UG, h->RSEL, h->PMAX), dim3(h->n_wg),
-                                       dim3(WG_THREADS * h->UG), args, 0, st));
+    HIP_TRY(hipLaunchCooperativeKernel(persistent_kernel(mode, h->UG, h->RSEL, h->PMAX, series != nullptr),
+                                       dim3(h->n_wg), dim3(WG_THREADS * h->UG), args, 0, st));
     if (step_ptr) {
         hipLaunchKernelGGL(advance_u64, dim3(1), dim3(64), 0, st, h->step_dev, (unsigned long long)nsteps);
         HIP_TRY(hipGetLastError());
@@ -728,11 +789,21 @@ int llg_autotune(llg_disk h, const float* m, const llg_params* p, int integrator
     if (probe_steps < 1) return fail(LLG_EINVAL, "probe_steps < 1");
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(hipStreamSynchronize(st));
-    float* work = nullptr;
-    HIP_TRY(hipMalloc(&work, h->state_size * sizeof(float)));
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
+    // probe buffer and timing events, released on every return path
+    struct Probe {
+        float* work = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Probe() {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            if (work) (void)hipFree(work);
+        }
+    } pr;
+    HIP_TRY(hipMalloc(&pr.work, h->state_size * sizeof(float)));
+    HIP_TRY(hipEventCreate(&pr.e0));
+    HIP_TRY(hipEventCreate(&pr.e1));
+    float* work = pr.work;
+    hipEvent_t e0 = pr.e0, e1 = pr.e1;
     const int mode = integrator == 0 ? MODE_RK4 : MODE_HEUN;
     llg_params* pp = const_cast<llg_params*>(p);
     if ((rc = upload_params(h, pp, st))) return rc;
@@ -770,9 +841,6 @@ int llg_autotune(llg_disk h, const float* m, const llg_params* p, int integrator
             bestc = c;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipFree(work);
     if ((rc = plan(h, bestc.UG, bestc.RSEL, nullptr, (1u << mode) | (1u << MODE_DEMAG), bestc.scale))) return rc;
     if (best_us) *best_us = best * 1e3 / (double)probe_steps;
     return 0;
@@ -816,7 +884,7 @@ int llg_rk4_vjp(llg_disk h, const float* rec, long long nsteps, float* ybar, dou
                 void* stream) {
     int rc = check_handle(h);
     if (rc) return rc;
-    if (!rec || !ybar || !pgrad) return fail(LLG_EINVAL, "null array");
+    if (!rec || !ybar || !pgrad || !p) return fail(LLG_EINVAL, "null argument");
     if (nsteps < 1) return fail(LLG_EINVAL, "nsteps < 1");
     for (int k = 0; k < h->n; ++k)
         if (p[k].renorm) return fail(LLG_EUNSUPPORTED, "the adjoint covers RK4 without renormalisation");
@@ -886,6 +954,65 @@ int llg_relax(llg_disk h, float* m, const double* X_nm, double cutoff_nm, double
                   rcut * rcut);
 }
 
+int llg_rk4_series(llg_disk h, float* m, long long nsteps, const llg_params* p, long long sample_every,
+                   double* series, void* stream) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!m || !series) return fail(LLG_EINVAL, "null array");
+    if (nsteps < 0) return fail(LLG_EINVAL, "nsteps < 0");
+    if (sample_every < 1 || sample_every > (1ll << 30)) return fail(LLG_EINVAL, "sample_every must be in [1, 2^30]");
+    if (nsteps == 0) return 0;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = upload_params(h, p, st))) return rc;
+    return launch(h, MODE_RK4, m, nullptr, nsteps, 0, 0, 0, st, nullptr, nullptr, nullptr, 0.0, 0.0, nullptr, 0.0,
+                  series, sample_every);
+}
+
+int llg_heun_series(llg_disk h, float* m, long long nsteps, unsigned long long seed, unsigned long long step0,
+                    unsigned int replica, const llg_params* p, long long sample_every, double* series,
+                    void* stream) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!m || !series) return fail(LLG_EINVAL, "null array");
+    if (nsteps < 0) return fail(LLG_EINVAL, "nsteps < 0");
+    if (sample_every < 1 || sample_every > (1ll << 30)) return fail(LLG_EINVAL, "sample_every must be in [1, 2^30]");
+    if (nsteps == 0) return 0;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = upload_params(h, p, st))) return rc;
+    const bool counter = step0 == LLG_STEP_COUNTER;
+    return launch(h, MODE_HEUN, m, nullptr, nsteps, seed, counter ? 0 : step0, replica, st, nullptr, nullptr, nullptr,
+                  0.0, 0.0, counter ? h->step_dev : nullptr, 0.0, series, sample_every);
+}
+
+int llg_power_spectrum(const double* x, int n_seq, long long bstride, long long len, long long tstride,
+                       int remove_mean, int window, double* work, double* out, void* stream) {
+    if (!x || !work || !out) return fail(LLG_EINVAL, "null array");
+    if (n_seq < 1 || n_seq > 65535) return fail(LLG_EINVAL, "n_seq must be in [1, 65535]");
+    if (len < 16 || len > (1ll << 24) || (len & (len - 1))) return fail(LLG_EINVAL, "len must be a power of two in [16, 2^24]");
+    if (tstride < 1 || bstride < 0) return fail(LLG_EINVAL, "need tstride >= 1 and bstride >= 0");
+    if (window != 0 && window != 1) return fail(LLG_EINVAL, "window: 0 = none, 1 = Hann");
+    hipStream_t st = (hipStream_t)stream;
+    double2* A = reinterpret_cast<double2*>(work);
+    double2* B = A + (size_t)len * n_seq;
+    const int half_blocks = (int)std::min<long long>((len / 2 + 255) / 256, 65535);
+    const int full_blocks = (int)std::min<long long>((len + 255) / 256, 65535);
+    hipLaunchKernelGGL(ps_mean, dim3(n_seq), dim3(256), 0, st, x, bstride, len, tstride, remove_mean, B);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(ps_load, dim3(full_blocks, n_seq), dim3(256), 0, st, x, bstride, len, tstride, window,
+                       (const double2*)B, A);
+    HIP_TRY(hipGetLastError());
+    double2* in = A;
+    double2* outb = B;
+    for (long long Ns = 1; Ns < len; Ns *= 2) {
+        hipLaunchKernelGGL(ps_pass, dim3(half_blocks, n_seq), dim3(256), 0, st, (const double2*)in, outb, len, Ns);
+        HIP_TRY(hipGetLastError());
+        std::swap(in, outb);
+    }
+    hipLaunchKernelGGL(ps_power, dim3(full_blocks, n_seq), dim3(256), 0, st, (const double2*)in, len, out);
+    HIP_TRY(hipGetLastError());
+    return 0;
+}
+
 int llg_heun_step(llg_disk h, float* m, long long nsteps, unsigned long long seed, unsigned long long step0,
                   unsigned int replica, const llg_params* p, void* stream) {
     int rc = check_handle(h);
@@ -930,8 +1057,20 @@ int llg_graph_create(llg_disk h, int integrator, float* m, long long nsteps, con
     // the graph keeps its own copy of the parameters
     if ((rc = upload_params(h, p, nullptr))) return rc;
     HIP_TRY(hipDeviceSynchronize());
-    HIP_TRY(hipMalloc(&g->prm, h->n * sizeof(DiskPrm)));
-    HIP_TRY(hipMemcpy(g->prm, h->prm_dev, h->n * sizeof(DiskPrm), hipMemcpyDeviceToDevice));
+    DiskPrm* gprm = nullptr;
+    HIP_TRY(g->dalloc(&gprm, h->n));
+    HIP_TRY(hipMemcpy(gprm, h->prm_dev, h->n * sizeof(DiskPrm), hipMemcpyDeviceToDevice));
+    // ... and of the current launch plan
+    int *gw2d = nullptr, *gw2l = nullptr;
+    DiskDesc* gdesc = nullptr;
+    HIP_TRY(g->dalloc(&gw2d, h->n_wg));
+    HIP_TRY(g->dalloc(&gw2l, h->n_wg));
+    HIP_TRY(hipMemcpy(gw2d, h->wg2disk, h->n_wg * sizeof(int), hipMemcpyDeviceToDevice));
+    HIP_TRY(hipMemcpy(gw2l, h->wg2local, h->n_wg * sizeof(int), hipMemcpyDeviceToDevice));
+    std::vector<DiskDesc> desc = h->desc;
+    for (DiskDesc& d : desc) HIP_TRY(g->dalloc(&d.part, (size_t)PART_STRIDE * d.G));
+    HIP_TRY(g->dalloc(&gdesc, h->n));
+    HIP_TRY(hipMemcpy(gdesc, desc.data(), h->n * sizeof(DiskDesc), hipMemcpyHostToDevice));
     HIP_TRY(hipGraphCreate(&g->graph, 0));
     // node 1: clear the barrier counters (a kernel, not a memset node)
     int n_bars = h->n_bars;
@@ -946,8 +1085,11 @@ int llg_graph_create(llg_disk h, int integrator, float* m, long long nsteps, con
     HIP_TRY(hipGraphAddKernelNode(&nz, g->graph, nullptr, 0, &zp));
     // node 2: the persistent cooperative launch
     const int mode = integrator == 0 ? MODE_RK4 : MODE_HEUN;
-    KArgs a = make_args(h, g->prm, mode, m, nullptr, nsteps, seed, 0, replica, integrator == 1 ? h->step_dev : nullptr,
+    KArgs a = make_args(h, gprm, mode, m, nullptr, nsteps, seed, 0, replica, integrator == 1 ? h->step_dev : nullptr,
                         nullptr, nullptr, nullptr, 0.0, 0.0);
+    a.disks = gdesc;
+    a.wg2disk = gw2d;
+    a.wg2local = gw2l;
     void* pargs[] = {&a};
     hipKernelNodeParams kp{};
     kp.func = const_cast<void*>(persistent_kernel(mode, h->UG, h->RSEL, h->PMAX));

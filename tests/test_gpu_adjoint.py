@@ -21,8 +21,10 @@ def dev(a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda").reshape(-1).contiguous()
 
 
+# up to P = 128, the P = 256 instance of the R = 80 nm adjoint workload, and P = 512
 @pytest.mark.parametrize("R,L,nsteps,pol", [(15.0, 5.0, 3, 0), (30.0, 10.0, 5, 0), (61.0, 12.0, 2, 0),
-                                            (30.0, 10.0, 5, 3)])
+                                            (30.0, 10.0, 5, 3), (80.0, 10.0, 3, 0), (80.0, 10.0, 2, 1),
+                                            (250.0, 20.0, 1, 0)])
 def test_rk4_vjp_matches_oracle(R, L, nsteps, pol):
     # pol 3: the recording integrator runs lane-group columns, the adjoint kernel its own strategy
     from paper_1207_2192_amd import Disk, LLGParams
@@ -56,7 +58,8 @@ def test_rk4_vjp_matches_oracle(R, L, nsteps, pol):
 
 
 @pytest.mark.parametrize("R,L,nsteps,renorm,fd", [(15.0, 5.0, 4, False, False), (30.0, 10.0, 6, True, False),
-                                                  (41.0, 8.0, 3, True, True)])
+                                                  (41.0, 8.0, 3, True, True), (80.0, 10.0, 2, True, False),
+                                                  (250.0, 20.0, 1, True, False)])
 def test_heun_vjp_matches_oracle(R, L, nsteps, renorm, fd):
     # reverse pass of Heun steps with the noise replayed, against autograd through the oracle
     from paper_1207_2192_amd import Disk, LLGParams

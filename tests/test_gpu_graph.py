@@ -76,3 +76,26 @@ def test_eager_heun_with_the_step_counter_equals_explicit_steps():
     disk.check()
     assert disk.get_step() == 15
     assert torch.equal(m1, m2)
+
+
+def test_graph_keeps_its_launch_plan_across_a_retune():
+    # a graph copies the plan (workgroup maps, descriptors, partial sums) at creation:
+    # re-planning the handle afterwards must neither disturb nor invalidate it
+    from paper_1207_2192_amd import LLGParams
+    disk, m0 = ragged()
+    p = [LLGParams(alpha=0.02, c=C_PY, dtau=0.04)] * disk.n
+    mg, me = m0.clone(), m0.clone()
+    g = disk.graph("rk4", mg, 12, p)
+    shape0 = disk.launch_shape()
+    for rep, (ug, wg, pol) in enumerate([(2, [1, 2, 3], 1), (4, None, 3), (1, [5, 1, 2], 2)]):
+        disk.tune(ug, wg, pol)
+        assert disk.launch_shape() != shape0 or rep > 0
+        g.launch()
+        other_work()
+        disk.rk4_step(me, 12, p)        # eager steps under the new plan
+        torch.cuda.synchronize()
+        disk.check()
+        # the radix schedule of the plans differs, so equal to float rounding only
+        assert float((mg - me).abs().max()) <= 1e-5, rep
+        me.copy_(mg)
+    g.close()
