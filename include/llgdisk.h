@@ -322,6 +322,23 @@ int llg_vortex_core_position(llg_disk h, const float* m, double lambda_ex_nm,
 /* Spatial average <m> per disk (Sec. IV): out[3k..3k+2], float64. */
 int llg_mean_m(llg_disk h, const float* m, double* out, void* stream);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): llg_rk4_step whose
+ * workspaces (stage states, RK4 accumulator, row/column spectra, barrier
+ * counters, descriptor table) live in a fixed array of LLG_NOALLOC_BYTES
+ * bytes inside the library instead of the handle's own buffers.  The array
+ * exists once per GPU for the life of the process; its address is looked up
+ * on the first call on a device.  The call allocates nothing (the handle,
+ * created earlier, supplies the geometry, kernel spectra and launch plan) and
+ * returns LLG_EINVAL, before enqueueing anything, when the handle needs more
+ * than LLG_NOALLOC_BYTES (llg_noalloc_bytes tells how much; a single disk up
+ * to D = 256 needs at most about 5 MB).  Results equal llg_rk4_step's.  All
+ * calls on one GPU share the array: calls that overlap on one GPU (several
+ * streams, several threads) race and must be serialised by the caller. */
+#define LLG_NOALLOC_BYTES (32ll << 20)
+long long llg_noalloc_bytes(llg_disk h);
+int llg_rk4_step_noalloc(llg_disk h, float* m, long long nsteps, const llg_params* p, void* stream);
+
 /* Synchronise the stream and report a device-side failure recorded since the
  * last check (LLG_EDEVICE) or 0. */
 int llg_check(llg_disk h, void* stream);

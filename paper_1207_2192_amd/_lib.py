@@ -61,6 +61,8 @@ SIGNATURES = {
     "llg_energy": (c_int, [c_vp, c_vp, ctypes.POINTER(LLGParamsC), c_vp, c_vp]),
     "llg_vortex_core_position": (c_int, [c_vp, c_vp, c_double, P_double, c_vp, c_vp]),
     "llg_mean_m": (c_int, [c_vp, c_vp, c_vp, c_vp]),
+    "llg_noalloc_bytes": (c_ll, [c_vp]),
+    "llg_rk4_step_noalloc": (c_int, [c_vp, c_vp, c_ll, ctypes.POINTER(LLGParamsC), c_vp]),
     "llg_check": (c_int, [c_vp, c_vp]),
     "llg_destroy": (None, [c_vp]),
     "llg_last_error": (ctypes.c_char_p, []),

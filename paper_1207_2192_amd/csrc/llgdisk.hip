@@ -13,6 +13,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <tuple>
@@ -662,6 +663,7 @@ int launch(llg_disk h, int mode, float* m, float* out, long long nsteps, unsigne
            unsigned long long step0, unsigned int replica0, hipStream_t st, float* rec = nullptr,
            const double* relax_x = nullptr, double* relax_out = nullptr, double kappa = 0.0, double tol = 0.0,
            const unsigned long long* step_ptr = nullptr, double relax_cut2 = 0.0,
+           const DiskDesc* desc_override = nullptr, unsigned int* bars_override = nullptr,
            double* series = nullptr, long long every = 0) {
     const int kmode = (mode == MODE_RHS || mode == MODE_ENERGY) ? MODE_DEMAG : mode;   // kernel of the mode
     if (!(h->plan_modes & (1u << kmode))) {
@@ -686,10 +688,11 @@ int launch(llg_disk h, int mode, float* m, float* out, long long nsteps, unsigne
                                               std::to_string(ncu * b) + "); re-plan with llg_tune");
     }
     const int nb = (h->n_bars + 255) / 256;
-    hipLaunchKernelGGL(zero_u32, dim3(nb), dim3(256), 0, st, h->bars, h->n_bars);
+    hipLaunchKernelGGL(zero_u32, dim3(nb), dim3(256), 0, st, bars_override ? bars_override : h->bars, h->n_bars);
     HIP_TRY(hipGetLastError());
     KArgs a = make_args(h, h->prm_dev, mode, m, out, nsteps, seed, step0, replica0, step_ptr, rec, relax_x,
                         relax_out, kappa, tol, relax_cut2);
+    if (desc_override) a.disks = desc_override;
     a.series = series;
     a.every = (int)every;
     void* args[] = {&a};
@@ -699,6 +702,62 @@ int launch(llg_disk h, int mode, float* m, float* out, long long nsteps, unsigne
         hipLaunchKernelGGL(advance_u64, dim3(1), dim3(64), 0, st, h->step_dev, (unsigned long long)nsteps);
         HIP_TRY(hipGetLastError());
     }
+    return 0;
+}
+
+// ---------------------------------------------------------------- fixed scratch array
+// Workspaces of llg_rk4_step_noalloc: one array per GPU for the life of the
+// process.  Layout (every block 256-byte aligned): the descriptor table of the
+// handle's disks, the barrier counters (one 128-byte line per disk), then per
+// disk the stage states A and B, the RK4 accumulator, the row/column spectra
+// and the per-workgroup partial sums.
+static __device__ __align__(256) unsigned char scratch[LLG_NOALLOC_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+__host__ __device__ inline unsigned long long align256(unsigned long long b) { return (b + 255ull) & ~255ull; }
+__host__ __device__ inline unsigned long long scratch_head(int n) {
+    return align256((unsigned long long)n * sizeof(DiskDesc)) + align256((unsigned long long)n * 32 * sizeof(unsigned));
+}
+__host__ __device__ inline unsigned long long scratch_disk_bytes(int D, int H, int Dp, int G) {
+    const unsigned long long st = align256((unsigned long long)3 * D * D * sizeof(float));
+    return 3 * st + align256((unsigned long long)3 * H * Dp * sizeof(float2)) +
+           align256((unsigned long long)PART_STRIDE * G * sizeof(double));
+}
+
+// Descriptor table in the scratch array: disk k as in the handle's table, its
+// workspaces redirected into its block (offsets summed over the disks before it).
+__global__ void scratch_descriptors(const DiskDesc* src, int n, unsigned char* base) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    unsigned long long off = scratch_head(n);
+    for (int q = 0; q < k; ++q) off += scratch_disk_bytes(src[q].D, src[q].H, src[q].Dp, src[q].G);
+    DiskDesc d = src[k];
+    const unsigned long long st = align256((unsigned long long)3 * d.D * d.D * sizeof(float));
+    unsigned char* p = base + off;
+    d.ya = reinterpret_cast<float*>(p);
+    d.yb = reinterpret_cast<float*>(p + st);
+    d.acc = reinterpret_cast<float*>(p + 2 * st);
+    d.aux = nullptr;
+    d.S = reinterpret_cast<float2*>(p + 3 * st);
+    d.part = reinterpret_cast<double*>(p + 3 * st + align256((unsigned long long)3 * d.H * d.Dp * sizeof(float2)));
+    d.bar = reinterpret_cast<unsigned int*>(base + align256((unsigned long long)n * sizeof(DiskDesc))) + 32 * k;
+    reinterpret_cast<DiskDesc*>(base)[k] = d;
+}
+
+// Device address of this device's scratch array, looked up once per device.
+int scratch_ptr(int dev, unsigned char** out) {
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(LLG_EUNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(LLG_EHIP, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
     return 0;
 }
 
@@ -871,6 +930,35 @@ int llg_rk4_step(llg_disk h, float* m, long long nsteps, const llg_params* p, vo
     return launch(h, MODE_RK4, m, nullptr, nsteps, 0, 0, 0, (hipStream_t)stream);
 }
 
+long long llg_noalloc_bytes(llg_disk h) {
+    if (!h) return fail(LLG_EINVAL, "null handle");
+    unsigned long long b = scratch_head(h->n);
+    for (const DiskDesc& d : h->desc) b += scratch_disk_bytes(d.D, d.H, d.Dp, d.G);
+    return (long long)b;
+}
+
+int llg_rk4_step_noalloc(llg_disk h, float* m, long long nsteps, const llg_params* p, void* stream) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!m) return fail(LLG_EINVAL, "null array");
+    if (nsteps < 0) return fail(LLG_EINVAL, "nsteps < 0");
+    const long long need = llg_noalloc_bytes(h);
+    if (need > (long long)LLG_NOALLOC_BYTES)
+        return fail(LLG_EINVAL, "the handle's workspaces need " + std::to_string(need) + " bytes, more than the " +
+                                    std::to_string((long long)LLG_NOALLOC_BYTES) +
+                                    " bytes of the fixed scratch array; use llg_rk4_step");
+    if (nsteps == 0) return 0;
+    unsigned char* base = nullptr;
+    if ((rc = scratch_ptr(h->device, &base))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = upload_params(h, p, st))) return rc;
+    hipLaunchKernelGGL(scratch_descriptors, dim3((h->n + 63) / 64), dim3(64), 0, st, h->desc_dev, h->n, base);
+    HIP_TRY(hipGetLastError());
+    unsigned int* bars = reinterpret_cast<unsigned int*>(base + align256((unsigned long long)h->n * sizeof(DiskDesc)));
+    return launch(h, MODE_RK4, m, nullptr, nsteps, 0, 0, 0, st, nullptr, nullptr, nullptr, 0.0, 0.0, nullptr, 0.0,
+                  reinterpret_cast<const DiskDesc*>(base), bars);
+}
+
 int llg_rk4_record(llg_disk h, float* m, long long nsteps, const llg_params* p, float* rec, void* stream) {
     int rc = check_handle(h);
     if (rc) return rc;
@@ -965,7 +1053,7 @@ int llg_rk4_series(llg_disk h, float* m, long long nsteps, const llg_params* p, 
     hipStream_t st = (hipStream_t)stream;
     if ((rc = upload_params(h, p, st))) return rc;
     return launch(h, MODE_RK4, m, nullptr, nsteps, 0, 0, 0, st, nullptr, nullptr, nullptr, 0.0, 0.0, nullptr, 0.0,
-                  series, sample_every);
+                  nullptr, nullptr, series, sample_every);
 }
 
 int llg_heun_series(llg_disk h, float* m, long long nsteps, unsigned long long seed, unsigned long long step0,
@@ -981,7 +1069,7 @@ int llg_heun_series(llg_disk h, float* m, long long nsteps, unsigned long long s
     if ((rc = upload_params(h, p, st))) return rc;
     const bool counter = step0 == LLG_STEP_COUNTER;
     return launch(h, MODE_HEUN, m, nullptr, nsteps, seed, counter ? 0 : step0, replica, st, nullptr, nullptr, nullptr,
-                  0.0, 0.0, counter ? h->step_dev : nullptr, 0.0, series, sample_every);
+                  0.0, 0.0, counter ? h->step_dev : nullptr, 0.0, nullptr, nullptr, series, sample_every);
 }
 
 int llg_power_spectrum(const double* x, int n_seq, long long bstride, long long len, long long tstride,
