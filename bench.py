@@ -36,7 +36,8 @@ C_PY = 0.14298555          # a^2/lambda_ex^2, Permalloy, a = 2 nm
 METRIC = "LLG cell-steps/s incl. FFT demag, batched vs plain; adjoint/forward time ratio"
 KERNEL_SOURCES = ["paper_1207_2192_amd/csrc/llg_kernels.hpp", "paper_1207_2192_amd/csrc/fft_lds.hpp",
                   "paper_1207_2192_amd/csrc/llg_device.hpp", "paper_1207_2192_amd/csrc/kernels_rk4.hip",
-                  "paper_1207_2192_amd/csrc/kernels_heun.hip"]
+                  "paper_1207_2192_amd/csrc/kernels_heun.hip", "paper_1207_2192_amd/csrc/kernels_rk4_series.hip",
+                  "paper_1207_2192_amd/csrc/kernels_heun_series.hip"]
 SEED = 20120827
 
 
@@ -107,11 +108,18 @@ def start_states(D_list, starts, a=2.0):
     return [li.vortex_ansatz(D, x0 / a + 0.01, y0 / a + 0.013) for D, (x0, y0) in zip(D_list, starts)]
 
 
-def step_call(disk, m, k, prms, integrator, step0, replica0=0):
+def step_call(disk, m, k, prms, integrator, step0, replica0=0, series_every=0):
+    """k integrator steps; with series_every > 0 the launch also records the float64
+    <m> and energy of the state at the start of every series_every-th step."""
+    if series_every:
+        if integrator == "rk4":
+            return disk.rk4_series(m, k, prms, series_every)
+        return disk.heun_series(m, k, prms, series_every, seed=SEED, step0=step0, replica=replica0)
     if integrator == "rk4":
         disk.rk4_step(m, k, prms)
     else:
         disk.heun_step(m, k, prms, seed=SEED, step0=step0, replica=replica0)
+    return None
 
 
 # ---------------------------------------------------------------- CPU oracle
@@ -182,6 +190,10 @@ def batched_vs_plain(steps, warmup):
         for j, dj in enumerate(plain):
             dj.rk4_step(mp[batch.offsets[j]:batch.offsets[j] + 3 * batch.D[j] ** 2], k, prms[j])
 
+    # untimed spin-up on a scratch copy after the host-side set-up of the plain handles
+    scratch = m0.clone()
+    batch.rk4_step(scratch, max(1, int(30e3 / max(tuned, 1.0))), prms)
+    del scratch
     tb = timed(run_batch)
     tp = timed(run_plain)
     batch.check()
@@ -267,6 +279,12 @@ def main():
     ap.add_argument("--plain", action="store_true", help="loop over single-disk handles instead of one batch")
     ap.add_argument("--sample-every", type=int, default=100,
                     help="steps between observable samples (core position + energy) in the timed region; 0 = none")
+    ap.add_argument("--series-energy", action="store_true",
+                    help="sample the energy from the integrator's own float64 series instead of llg_energy "
+                         "(an extra field evaluation)")
+    ap.add_argument("--spinup-ms", type=float, default=30.0,
+                    help="untimed integrator work on a scratch copy of the state right before the warmup "
+                         "(brings the GPU clocks up after the host-side set-up)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -316,13 +334,16 @@ def main():
             if timed:
                 ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                 ev[0].record(stream)
+            # in the timed region the energy and <m> of every launch's start state come
+            # from the integrator's own series (unless --separate-energy)
+            ser_every = k if (timed and args.sample_every and args.series_energy) else 0
             if plain is not None:
                 for j, dj in enumerate(plain):
                     mj = m[disk.offsets[j]:disk.offsets[j] + 3 * disk.D[j] ** 2]
                     step_call(dj, mj, k, prms[j], integrator, step_counter[0], j)
                     launches += 1
             else:
-                step_call(disk, m, k, prms, integrator, step_counter[0])
+                ser = step_call(disk, m, k, prms, integrator, step_counter[0], series_every=ser_every)
                 launches += 1
             if timed:
                 ev[1].record(stream)
@@ -332,6 +353,8 @@ def main():
                         for j, dj in enumerate(plain):
                             mj = m[disk.offsets[j]:disk.offsets[j] + 3 * disk.D[j] ** 2]
                             samples.append((dj.vortex_core_position(mj, lam_nm), dj.energy(mj, eprm[j:j + 1])))
+                    elif args.series_energy:
+                        samples.append((disk.vortex_core_position(m, lam_nm), ser))
                     else:
                         samples.append((disk.vortex_core_position(m, lam_nm), disk.energy(m, eprm)))
             step_counter[0] += k
@@ -339,6 +362,14 @@ def main():
         return launches
 
     e0 = disk.energy(m, eprm)[:, 0].cpu()
+    # untimed spin-up on a scratch copy (the state itself is untouched), then the warmup steps
+    spin = 0
+    if args.spinup_ms > 0 and plain is None:
+        per_us = tuned_us if tuned_us else 300.0
+        spin = max(1, int(math.ceil(args.spinup_ms * 1e3 / per_us)))
+        scratch = m.clone()
+        step_call(disk, scratch, spin, prms, integrator, 10 ** 9)
+        del scratch
     if args.warmup:
         run(args.warmup)
     torch.cuda.synchronize()
@@ -395,6 +426,8 @@ def main():
                    "workgroups": shape[1], "threads_per_workgroup": shape[2],
                    "radix_policy": shape[3], "autotuned": tuned_us is not None,
                    "observables_every": args.sample_every, "observable_samples": len(samples),
+                   "energy_from": "integrator float64 series" if args.series_energy else "llg_energy",
+                   "spinup_steps_on_scratch_copy": spin,
                    "integrator_share_of_time": kernel_s / gpu_s},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

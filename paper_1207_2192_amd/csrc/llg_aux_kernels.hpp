@@ -111,6 +111,30 @@ __global__ __launch_bounds__(OBS_THREADS) void mean_kernel(const DiskDesc* disks
     }
 }
 
+// Vortex core position (Sec. IV) in two kernels.
+//
+// core_scan_kernel: block (s, k) scans the plaquette rows [CORE_ROWS s,
+// CORE_ROWS (s + 1)) of disk k.  A plaquette counts when its four cells belong
+// to the disk; its winding is the sum of the four counter-clockwise angle
+// differences, each wrapped into [-pi, pi), over 2 pi, rounded.  The angles are
+// taken in float32 first; only when a raw difference lies within
+// CORE_WRAP_MARGIN of +-pi (where float32 rounding could flip the wrap) is the
+// plaquette recomputed with float64 angles, so every decision equals the
+// float64 one.  The block writes its count of +1 plaquettes and its best
+// candidate (score: closeness to the hint, else the sum of m_z^2 over the
+// corners; ties to the lower plaquette index) to part[k][s].
+// core_finish_kernel: one block per disk picks r_v from the strips (same
+// order), then forms the m_z^2-weighted centroid over the disk cells within
+// the cutoff of r_v (scanning only the cutoff's bounding box) or, without a
+// +1 plaquette, over the whole disk.  float64 throughout the reductions.
+constexpr int CORE_ROWS = 8;
+constexpr float CORE_WRAP_MARGIN = 1e-3f;
+
+struct CorePart {
+    double score;
+    int count, idx;
+};
+
 __device__ __forceinline__ double wrap_pi(double x) {
     // x + pi reduced into [0, 2 pi), minus pi
     const double two_pi = 6.283185307179586476925286766559;
@@ -120,57 +144,80 @@ __device__ __forceinline__ double wrap_pi(double x) {
     return t - pi;
 }
 
-// Vortex core position per disk, float64 (one workgroup per disk).
+// Winding of the plaquette with corners a, b, c, d (counter-clockwise).
+__device__ __forceinline__ int plaquette_winding(const float* mx, const float* my, int ca, int cb, int cc, int cd) {
+    const float pi_f = 3.14159265358979f;
+    const float fa = atan2f(my[ca], mx[ca]), fb = atan2f(my[cb], mx[cb]);
+    const float fc = atan2f(my[cc], mx[cc]), fd = atan2f(my[cd], mx[cd]);
+    const float r0 = fb - fa, r1 = fc - fb, r2 = fd - fc, r3 = fa - fd;
+    const float lo = pi_f - CORE_WRAP_MARGIN, hi = pi_f + CORE_WRAP_MARGIN;
+    auto near_pi = [&](float r) {
+        const float q = fabsf(r);
+        return q > lo && q < hi;
+    };
+    if (!(near_pi(r0) || near_pi(r1) || near_pi(r2) || near_pi(r3))) {
+        auto wrap = [&](float r) { return r >= pi_f ? r - 2.f * pi_f : (r < -pi_f ? r + 2.f * pi_f : r); };
+        const float s = wrap(r0) + wrap(r1) + wrap(r2) + wrap(r3);
+        return (int)rintf(s * 0.15915494309189535f);
+    }
+    const double two_pi = 6.283185307179586476925286766559;
+    const double ga = atan2((double)my[ca], (double)mx[ca]), gb = atan2((double)my[cb], (double)mx[cb]);
+    const double gc = atan2((double)my[cc], (double)mx[cc]), gd = atan2((double)my[cd], (double)mx[cd]);
+    const double s = wrap_pi(gb - ga) + wrap_pi(gc - gb) + wrap_pi(gd - gc) + wrap_pi(ga - gd);
+    return (int)rint(s / two_pi);
+}
+
+__device__ __forceinline__ bool core_better(double s, int i, double bs, int bi) {
+    return s > bs || (s == bs && i < bi);
+}
+
 // hint: per disk (x, y) in nm, NaN = no hint.
-__global__ __launch_bounds__(OBS_THREADS) void core_kernel(const DiskDesc* disks, const float* m_base,
-                                                           const double* hint, double a_nm, double cutoff_cells,
-                                                           double* out) {
-    __shared__ double sh[OBS_THREADS / 64];
+__global__ __launch_bounds__(OBS_THREADS) void core_scan_kernel(const DiskDesc* disks, const float* m_base,
+                                                                const double* hint, double a_nm, int n_strips,
+                                                                CorePart* part) {
     __shared__ double s_score[OBS_THREADS / 64];
-    __shared__ int s_idx[OBS_THREADS / 64];
-    const int k = blockIdx.x;
+    __shared__ int s_idx[OBS_THREADS / 64], s_cnt[OBS_THREADS / 64];
+    const int k = blockIdx.y, strip = blockIdx.x;
     const DiskDesc d = disks[k];
     const int D = d.D, DD = D * D, Dm = D - 1;
     const float* m = m_base + d.m_off;
-    const unsigned char* mask = d.mask;
     const double half = (D - 1) / 2.0;
-    const double two_pi = 6.283185307179586476925286766559;
     const double hx = hint[2 * k], hy = hint[2 * k + 1];
     const bool use_hint = !(isnan(hx) || isnan(hy));
-
+    const int j0 = strip * CORE_ROWS, j1 = min(j0 + CORE_ROWS, Dm);
     double best = -INFINITY;
-    int best_idx = 0x7fffffff;
-    int nplus = 0;
-    for (int p = threadIdx.x; p < Dm * Dm; p += OBS_THREADS) {
-        const int j = p / Dm, i = p - j * Dm;
+    int best_idx = 0x7fffffff, nplus = 0;
+    const int nrow = j1 > j0 ? j1 - j0 : 0;
+    for (int q = threadIdx.x; q < nrow * Dm; q += OBS_THREADS) {
+        const int j = j0 + q / Dm, i = q % Dm;
+        const int x0 = 2 * i - (D - 1), y0 = 2 * j - (D - 1);   // doubled centre coordinates of cell (j, i)
+        const int x1 = x0 + 2, y1 = y0 + 2, DD2 = D * D;
+        // the four corners belong to the disk (cell centre inside or on the circle)
+        if (!(x0 * x0 + y0 * y0 <= DD2 && x1 * x1 + y0 * y0 <= DD2 && x1 * x1 + y1 * y1 <= DD2 &&
+              x0 * x0 + y1 * y1 <= DD2))
+            continue;
         const int ca = j * D + i, cb = ca + 1, cc = ca + D + 1, cd = ca + D;
-        if (!(mask[ca] && mask[cb] && mask[cc] && mask[cd])) continue;
-        const double fa = atan2((double)m[DD + ca], (double)m[ca]);
-        const double fb = atan2((double)m[DD + cb], (double)m[cb]);
-        const double fc = atan2((double)m[DD + cc], (double)m[cc]);
-        const double fd = atan2((double)m[DD + cd], (double)m[cd]);
-        const double s = wrap_pi(fb - fa) + wrap_pi(fc - fb) + wrap_pi(fd - fc) + wrap_pi(fa - fd);
-        if ((int)rint(s / two_pi) != 1) continue;
+        if (plaquette_winding(m, m + DD, ca, cb, cc, cd) != 1) continue;
         ++nplus;
+        const int p = j * Dm + i;
         double score;
-        const double cx = ((double)i - half) + 0.5, cy = ((double)j - half) + 0.5;
         if (use_hint) {
-            const double ddx = cx - hx / a_nm, ddy = cy - hy / a_nm;
+            const double ddx = ((double)i - half) + 0.5 - hx / a_nm, ddy = ((double)j - half) + 0.5 - hy / a_nm;
             score = -(ddx * ddx + ddy * ddy);
         } else {
             const double za = m[2 * DD + ca], zb = m[2 * DD + cb], zc = m[2 * DD + cc], zd = m[2 * DD + cd];
             score = za * za + zb * zb + zc * zc + zd * zd;
         }
-        if (score > best || (score == best && p < best_idx)) {
+        if (core_better(score, p, best, best_idx)) {
             best = score;
             best_idx = p;
         }
     }
-    // argmax (higher score, then lower index) over the workgroup
     for (int o = 32; o > 0; o >>= 1) {
         const double os = __shfl_xor(best, o, 64);
         const int oi = __shfl_xor(best_idx, o, 64);
-        if (os > best || (os == best && oi < best_idx)) {
+        nplus += __shfl_xor(nplus, o, 64);
+        if (core_better(os, oi, best, best_idx)) {
             best = os;
             best_idx = oi;
         }
@@ -179,33 +226,79 @@ __global__ __launch_bounds__(OBS_THREADS) void core_kernel(const DiskDesc* disks
     if (lane == 0) {
         s_score[wave] = best;
         s_idx[wave] = best_idx;
+        s_cnt[wave] = nplus;
     }
-    const double np = block_sum((double)nplus, sh);
-    double bs = s_score[0];
-    int bi = s_idx[0];
-    for (int w = 1; w < OBS_THREADS / 64; ++w)
-        if (s_score[w] > bs || (s_score[w] == bs && s_idx[w] < bi)) {
-            bs = s_score[w];
-            bi = s_idx[w];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double bs = s_score[0];
+        int bi = s_idx[0], cnt = s_cnt[0];
+        for (int w = 1; w < OBS_THREADS / 64; ++w) {
+            cnt += s_cnt[w];
+            if (core_better(s_score[w], s_idx[w], bs, bi)) {
+                bs = s_score[w];
+                bi = s_idx[w];
+            }
         }
-    const bool found = np > 0.5;
-    double xv = NAN, yv = NAN;
-    if (found) {
-        const int j = bi / Dm, i = bi - j * Dm;
-        xv = ((double)i - half) + 0.5;
-        yv = ((double)j - half) + 0.5;
+        part[k * n_strips + strip] = CorePart{bs, cnt, bi};
     }
+}
+
+__global__ __launch_bounds__(OBS_THREADS) void core_finish_kernel(const DiskDesc* disks, const float* m_base,
+                                                                  double a_nm, double cutoff_cells, int n_strips,
+                                                                  const CorePart* part, double* out) {
+    __shared__ double sh[OBS_THREADS / 64];
+    __shared__ double s_xv, s_yv;
+    __shared__ int s_found;
+    const int k = blockIdx.x;
+    const DiskDesc d = disks[k];
+    const int D = d.D, DD = D * D, Dm = D - 1;
+    const float* m = m_base + d.m_off;
+    const double half = (D - 1) / 2.0;
+    if (threadIdx.x == 0) {
+        double bs = -INFINITY;
+        int bi = 0x7fffffff, np = 0;
+        const int ns = (Dm + CORE_ROWS - 1) / CORE_ROWS;
+        for (int s = 0; s < ns; ++s) {
+            const CorePart c = part[k * n_strips + s];
+            np += c.count;
+            if (c.count > 0 && core_better(c.score, c.idx, bs, bi)) {
+                bs = c.score;
+                bi = c.idx;
+            }
+        }
+        s_found = np;
+        s_xv = NAN;
+        s_yv = NAN;
+        if (np > 0) {
+            const int j = bi / Dm, i = bi - j * Dm;
+            s_xv = ((double)i - half) + 0.5;
+            s_yv = ((double)j - half) + 0.5;
+        }
+    }
+    __syncthreads();
+    const bool found = s_found > 0;
+    const double xv = s_xv, yv = s_yv;
     const double c2 = cutoff_cells * cutoff_cells;
+    // cells to visit: the cutoff circle's bounding box, or the whole box
+    int i0 = 0, i1 = D - 1, j0 = 0, j1 = D - 1;
+    if (found) {
+        i0 = max(0, (int)floor(xv + half - cutoff_cells) - 1);
+        i1 = min(D - 1, (int)ceil(xv + half + cutoff_cells) + 1);
+        j0 = max(0, (int)floor(yv + half - cutoff_cells) - 1);
+        j1 = min(D - 1, (int)ceil(yv + half + cutoff_cells) + 1);
+    }
+    const int wdt = i1 - i0 + 1, hgt = j1 - j0 + 1;
     double sw = 0.0, swx = 0.0, swy = 0.0;
-    for (int c = threadIdx.x; c < DD; c += OBS_THREADS) {
-        if (!mask[c]) continue;
-        const int j = c / D, i = c - j * D;
+    for (int q = threadIdx.x; q < wdt * hgt; q += OBS_THREADS) {
+        const int j = j0 + q / wdt, i = i0 + q % wdt;
+        const int xx = 2 * i - (D - 1), yy = 2 * j - (D - 1);
+        if (xx * xx + yy * yy > D * D) continue;
         const double x = (double)i - half, y = (double)j - half;
         if (found) {
             const double ddx = x - xv, ddy = y - yv;
             if (!(ddx * ddx + ddy * ddy < c2)) continue;
         }
-        const double z = m[2 * DD + c];
+        const double z = m[2 * DD + j * D + i];
         const double w = z * z;
         sw += w;
         swx += w * x;
@@ -219,7 +312,7 @@ __global__ __launch_bounds__(OBS_THREADS) void core_kernel(const DiskDesc* disks
         out[5 * k + 1] = swy / sw * a_nm;
         out[5 * k + 2] = xv * a_nm;
         out[5 * k + 3] = yv * a_nm;
-        out[5 * k + 4] = np;
+        out[5 * k + 4] = (double)s_found;
     }
 }
 

@@ -177,6 +177,8 @@ struct llg_disk_s {
     int n_bars = 0;
     int* err_dev = nullptr;
     unsigned long long* step_dev = nullptr;   // Heun step counter (LLG_STEP_COUNTER)
+    CorePart* core_part = nullptr;    // per disk and plaquette-row strip: core-position candidates
+    int core_strips = 1;              // strips per disk in core_part
     unsigned plan_modes = 0;          // modes whose co-residency the current plan was checked for
     int UG = 1;                       // wavefront groups per workgroup of the persistent launch
     int RSEL = 0;                     // transform policy (radix and column strategy)
@@ -521,6 +523,12 @@ int create(int n, const double* R_nm, const double* L_nm, double a_nm, const int
     if ((rc = h->dalloc(&h->err_dev, 1))) return rc;
     HIP_TRY(hipMemset(h->err_dev, 0, sizeof(int)));
     if ((rc = h->dalloc(&h->step_dev, 1))) return rc;
+    {
+        int dmax = 1;
+        for (int D : h->D) dmax = std::max(dmax, D);
+        h->core_strips = std::max(1, (dmax - 1 + CORE_ROWS - 1) / CORE_ROWS);
+        if ((rc = h->dalloc(&h->core_part, (size_t)n * h->core_strips))) return rc;
+    }
     HIP_TRY(hipMemset(h->step_dev, 0, sizeof(unsigned long long)));
     h->desc.assign(n, DiskDesc{});
     for (int k = 0; k < n; ++k) {
@@ -1249,8 +1257,11 @@ int llg_vortex_core_position(llg_disk h, const float* m, double lambda_ex_nm, co
     for (int k = 0; k < 2 * h->n; ++k) h->hint_pin[k] = hint_nm ? hint_nm[k] : NAN;
     HIP_TRY(hipMemcpyAsync(h->hint_dev, h->hint_pin, 2 * h->n * sizeof(double), hipMemcpyHostToDevice, st));
     HIP_TRY(hipEventRecord(h->hint_event, st));
-    hipLaunchKernelGGL(core_kernel, dim3(h->n), dim3(OBS_THREADS), 0, st, h->desc_dev, m, h->hint_dev, h->a_nm,
-                       4.0 * lambda_ex_nm / h->a_nm, out);
+    hipLaunchKernelGGL(core_scan_kernel, dim3(h->core_strips, h->n), dim3(OBS_THREADS), 0, st, h->desc_dev, m,
+                       h->hint_dev, h->a_nm, h->core_strips, h->core_part);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(core_finish_kernel, dim3(h->n), dim3(OBS_THREADS), 0, st, h->desc_dev, m, h->a_nm,
+                       4.0 * lambda_ex_nm / h->a_nm, h->core_strips, h->core_part, out);
     HIP_TRY(hipGetLastError());
     return 0;
 }

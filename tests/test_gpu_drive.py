@@ -147,3 +147,14 @@ def test_pulse_without_width_is_rejected():
     m = dev(li.vortex_ansatz(disk.D[0], 1.0, 0.0))
     with pytest.raises(LLGError):
         disk.rk4_step(m, 2, LLGParams(c=C_PY, hpulse=(0.1, 0.0, 0.0), wpulse=0.0))
+
+
+def test_driven_resonance_and_ring_down_find_the_gyrotropic_frequency():
+    # experiments.drive_response: the response peak of an in-plane AC drive swept
+    # across frequency, and the spectral peak of the free ring-down after a field
+    # pulse, both near the Thiele frequency kt/(2 pi)^2 of the static stiffness
+    from experiments.drive_response import run
+    rep = run(30.0, 10.0, n_freq=12)
+    print(rep["sweep"]["peak_over_thiele"], rep["ringdown"]["peak_over_thiele"])
+    assert 0.8 < rep["sweep"]["peak_over_thiele"] < 1.3
+    assert 0.8 < rep["ringdown"]["peak_over_thiele"] < 1.3
