@@ -89,6 +89,18 @@ def rotational_speeds(t, x, y, lag):
     return np.abs(w) * np.hypot(xm, ym), w
 
 
+def angular_momentum_rate(t, x, y, lag):
+    """Omega = <x v_y - y v_x> / <r^2> over all samples and replicas, with the
+    velocities from centred differences over `lag` samples: the rotation rate
+    weighted by r^2, insensitive to the ill-defined azimuth of cores that pass
+    near the centre."""
+    dt = (t[2 * lag:] - t[:-2 * lag])[:, None]
+    vx = (x[2 * lag:] - x[:-2 * lag]) / dt
+    vy = (y[2 * lag:] - y[:-2 * lag]) / dt
+    xm, ym = x[lag:-lag], y[lag:-lag]
+    return float(np.mean(xm * vy - ym * vx) / np.mean(xm * xm + ym * ym))
+
+
 def bartlett(x, seg: int):
     """Average periodogram of the non-overlapping length-seg segments of the rows of x
     (mean removed per segment, no window); returns (P[k], number of segments)."""

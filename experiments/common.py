@@ -48,15 +48,20 @@ def sample_cores(disk: Disk, m, nsteps, every, step_fn, lam_nm, hint=True):
     from step n0) and sample the core position after each launch; returns
     (t_steps [S], cores [S, n, 5]) as numpy.  With hint, every sample uses the
     previous core position to choose among several +1 plaquettes."""
+    import time
     S = nsteps // every
     cores = torch.empty(S, disk.n, 5, dtype=torch.float64, device="cuda")
     prev = None
+    last = time.perf_counter()
     for s in range(S):
         step_fn(s * every, every)
         c = disk.vortex_core_position(m, lam_nm, hint_nm=prev)
         cores[s] = c
         if hint and s % 50 == 49:        # refresh the hint now and then (a host copy)
             prev = [tuple(v) for v in c[:, :2].cpu().numpy().tolist()]
+            if time.perf_counter() - last > 30.0:
+                last = time.perf_counter()
+                print(f"# {(s + 1) * every} / {S * every} steps", flush=True)
     torch.cuda.synchronize()
     disk.check()
     return (np.arange(1, S + 1) * every), cores.cpu().numpy()

@@ -35,8 +35,8 @@ import time
 import numpy as np
 import torch
 
-from experiments.analysis import (gyration_rate, radial_statistics, rayleigh_cdf, ks_distance, rotational_speeds,
-                                  stiffness_fit, stiffness_two_point, thiele_rate)
+from experiments.analysis import (angular_momentum_rate, radial_statistics, rayleigh_cdf, ks_distance,
+                                  rotational_speeds, stiffness_fit, stiffness_two_point, thiele_rate)
 from experiments.common import A_NM, PY, material, relax_batch, segment_spectra
 from paper_1207_2192_amd import Disk, LLGParams
 
@@ -111,6 +111,10 @@ def run(geoms, temps, *, replicas=16, alpha=0.02, dtau=0.04, tau=250000.0, every
     sx = series[int(equil * S * per):, :, 0].contiguous()
     P, nseg = segment_spectra(sx, seg)
     freqs = np.arange(seg // 2 + 1) / (seg * series_every * dtau)
+    # the gyrotropic line from four times longer segments (finer resolution, fewer segments)
+    seg_l = 4 * seg
+    P_l, nseg_l = segment_spectra(sx, seg_l) if sx.shape[0] >= seg_l else (None, 0)
+    freqs_l = np.arange(seg_l // 2 + 1) / (seg_l * series_every * dtau)
     report = {"geometries": [], "alpha": alpha, "dtau": dtau, "tau": nsteps * dtau, "replicas": replicas,
               "sample_every": every, "series_every": series_every, "equilibration_fraction": equil,
               "fd_factor": fd_factor, "run_s": run_s, "cell_steps_per_s": sum(disk.n_cells) * nsteps / run_s,
@@ -130,17 +134,35 @@ def run(geoms, temps, *, replicas=16, alpha=0.02, dtau=0.04, tau=250000.0, every
         lag = max(1, int(round(0.25 * 2 * math.pi / abs(om_thiele) / (every * dtau))))
         V, w = rotational_speeds(t[first:], x, y, lag)
         om_mean = float(np.mean(w))
+        om_L = angular_momentum_rate(t[first:], x, y, 1)
         v2_pred = 2.0 * T_eff * kt / (2 * math.pi) ** 2
-        speed = {"lag_tau": lag * every * dtau, "v2_measured": float(np.mean(V ** 2)), "v2_predicted": v2_pred,
-                 "ratio": float(np.mean(V ** 2) / v2_pred),
-                 "ks_distance": ks_distance(V, lambda v: rayleigh_cdf(v / abs(om_thiele), kt, T_eff)),
-                 "omega_mean": om_mean, "omega_thiele": om_thiele, "omega_ratio": om_mean / om_thiele}
+        # V = |Omega| r with the r^2-weighted rate (f(V) = p(V/Omega)/Omega), and the raw
+        # per-sample speeds r |d theta/dt| over the lag
+        VL = abs(om_L) * r
+        speed = {"lag_tau": lag * every * dtau, "v2_predicted": v2_pred,
+                 "v2_from_rate": float(np.mean(VL ** 2)), "ratio_from_rate": float(np.mean(VL ** 2) / v2_pred),
+                 "ks_distance_from_rate": ks_distance(VL, lambda v: rayleigh_cdf(v / abs(om_thiele), kt, T_eff)),
+                 "v2_raw": float(np.mean(V ** 2)), "ratio_raw": float(np.mean(V ** 2) / v2_pred),
+                 "omega_r2_weighted": om_L, "omega_mean_azimuth_rate": om_mean, "omega_thiele": om_thiele,
+                 "omega_ratio": om_L / om_thiele}
         Pq = P[cols].mean(axis=0)
         lo = (freqs > 0) & (freqs < 0.004)
         hi = (freqs > 0.004) & (freqs < 0.02)
         kg = int(np.argmax(np.where(lo, Pq, -1)))
+        nu_g, res_g = float(freqs[kg]), float(freqs[1])
+        if P_l is not None:
+            Pl = P_l[cols].mean(axis=0)
+            lo_l = (freqs_l > 0) & (freqs_l < 0.004)
+            kl = int(np.argmax(np.where(lo_l, Pl, -1)))
+            nu_g, res_g = float(freqs_l[kl]), float(freqs_l[1])
+            if 1 <= kl < len(Pl) - 1:          # parabola through the log power of the peak and its neighbours
+                a_, b_, c_ = np.log(Pl[kl - 1:kl + 2])
+                den = a_ - 2 * b_ + c_
+                if den < 0:
+                    nu_g = float(freqs_l[kl] + 0.5 * (a_ - c_) / den * freqs_l[1])
         spec = {"segment": seg, "segments_per_replica": nseg, "resolution": float(freqs[1]),
-                "gyrotropic_peak_nu": float(freqs[kg]), "gyrotropic_peak_GHz": float(freqs[kg] * F0_GHZ),
+                "gyrotropic_segment": seg_l if P_l is not None else seg, "gyrotropic_resolution": res_g,
+                "gyrotropic_peak_nu": nu_g, "gyrotropic_peak_GHz": nu_g * F0_GHZ,
                 "gyrotropic_thiele_GHz": abs(om_thiele) / (2 * math.pi) * F0_GHZ,
                 "nu": freqs[:int(0.02 / freqs[1]) + 1].tolist(), "power": Pq[:int(0.02 / freqs[1]) + 1].tolist()}
         if hi.any():
@@ -154,7 +176,7 @@ def run(geoms, temps, *, replicas=16, alpha=0.02, dtau=0.04, tau=250000.0, every
                                      "static": stat[gi], "radial": radial, "speed": speed, "spectrum": spec,
                                      "samples": int(r.size), "vortex_lost_samples": lost})
         log(f"# R={R} L={L} T={T} K: <r^2>/pred = {radial['ratio']:.3f}, KS = {radial['ks_distance']:.3f}, "
-            f"<V^2>/pred = {speed['ratio']:.3f}, Omega/Thiele = {speed['omega_ratio']:.3f}, "
+            f"<V^2>/pred = {speed['ratio_from_rate']:.3f}, Omega/Thiele = {speed['omega_ratio']:.3f}, "
             f"f_G peak {spec['gyrotropic_peak_GHz']:.3f} GHz (Thiele {spec['gyrotropic_thiele_GHz']:.3f}), "
             f"high peaks {spec.get('high_peaks_GHz')}")
     disk.close()

@@ -99,6 +99,9 @@ def run(geoms, *, dtau=0.04, tau_damped=1000.0, periods=6.0, max_steps=1_200_000
         lr = np.array([r["L_over_R"] for r in ok])
         kl = np.array([r["kF_over_L"] for r in ok])
         summary["kF_over_L_vs_L_over_R_slope"] = float(np.polyfit(lr, kl, 1)[0])
+        thin = lr <= 0.2
+        if thin.sum() >= 3:        # the range where eq. kFlinear is meant to hold
+            summary["kF_over_L_vs_L_over_R_slope_LR_le_0.2"] = float(np.polyfit(lr[thin], kl[thin], 1)[0])
         kx = np.array([-r["omega_thiele"] for r in ok])
         ky = np.array([-r["omega_measured"] for r in ok])
         summary["omega_vs_thiele_slope_through_0"] = float((kx * ky).sum() / (kx * kx).sum())

@@ -482,11 +482,12 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     set_field(pr.tau0);
     // stage times as fractions of a step: RK4 (0, 1/2, 1/2, 1), Heun (0, 1)
     auto stage_frac = [](int nst, int s) { return nst == 4 ? (s == 0 ? 0.0 : s == 3 ? 1.0 : 0.5) : (double)s; };
-    // observable series (kernel instances with SER only): per-thread float64
-    // sums of m and of the energy density of the state at the start of a
-    // sampled step (its field is the stage-0 field)
+    // observable series (kernel instances with SER only): float64 sums of m and
+    // of the energy density of the state at the start of a sampled step (its
+    // field is the stage-0 field), one slot per wavefront in LDS, so that no
+    // register is held across the transforms
     constexpr bool SERIES = SER && (MODE == MODE_RK4 || MODE == MODE_HEUN);
-    double sm[4] = {0.0, 0.0, 0.0, 0.0};
+    __shared__ double red4[SERIES ? 3 * MAX_UG : 1][4];
 
     // ---- per-cell work after the inverse transforms; new stage state back into LDS
     // stage s of step n; Ys = state whose field is in LDS; Yn = where the next stage state goes.
@@ -494,7 +495,10 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     // step's start state and the accumulator of the two cells of a column are
     // loaded into registers before the row spectra, so that all of the
     // iteration's loads share one memory latency.
-    const bool need_y0 = (mode == MODE_RK4) || (mode == MODE_HEUN);
+    // RK4: the step's start state at every stage.  Heun: at the corrector only,
+    // and there the slot carries the noise w stored by the predictor (the
+    // corrector's base m_n + Delta_1/2 comes from the accumulator)
+    auto need_y0 = [&](int s) { return mode == MODE_RK4 || (mode == MODE_HEUN && s == 1); };
     // stage record: per step, per stage, (stage state, demag field) of [3][D][D]
     constexpr int NST = (MODE == MODE_HEUN || MODE == MODE_HEUN_VJP) ? 2 : 4;
     float* const recd = a.rec ? a.rec + (size_t)a.nsteps * (2 * NST) * (size_t)d.m_off : nullptr;
@@ -519,9 +523,48 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         }
     };
     Gath gv[IC];
+    // this thread's cells of row iteration b (the cell-update items): m from the
+    // staged rows, H from the inverse transforms, added to the wavefront's slots
+    auto sample_pass = [&](int b) {
+        double q4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < IC; ++q) {
+            int uu, i;
+            if (!cell_item(tid<OPQ>() + q * NT, uu, i)) continue;
+            const int p = b * U + uu;
+            if (p >= d.n_pairs) continue;
+            const float2 hz2 = BUF(2, uu)[padb(i)];
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int j = 2 * p + r;
+                if (j >= D || !in_disk(j, i, D)) continue;
+                const float2 hxy = BUF(r, uu)[padb(i)];
+                const double H3[3] = {(double)hxy.x, (double)hxy.y, (double)(r == 0 ? hz2.x : hz2.y)};
+                const double h3[3] = {hxd, hyd, hzd};
+                double ex = 0.0, ed = 0.0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float* hr = halo + (c * HR + 2 * uu + r) * HW + 1 + i;   // row j - 1 of the stage
+                    const double mc = hr[HW];
+                    const double e3 = (double)hr[0] + (double)hr[2 * HW] + (double)hr[HW - 1] + (double)hr[HW + 1];
+                    q4[c] += mc;
+                    ex += mc * e3;
+                    ed += mc * (h3[c] + 0.5 * H3[c]);
+                }
+                q4[3] += -0.5 * ex - pr.c_d * ed;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const double v = wave_sum(q4[c]);
+            if (lane == 0) red4[wv][c] += v;
+        }
+    };
     auto gather = [&](int b, int s) {
         const bool need_acc = (mode == MODE_RK4 && s > 0) || (mode == MODE_HEUN && s == 1);
-        const __amdgpu_buffer_rsrc_t Mrs = make_rsrc(m, (unsigned)(3 * DD) * 4u);
+        const bool heun = mode == MODE_HEUN;
+        const __amdgpu_buffer_rsrc_t Mrs = make_rsrc(heun ? d.aux : m, (unsigned)(3 * DD) * 4u);
+        const bool ny0 = need_y0(s);
         const __amdgpu_buffer_rsrc_t Ars = make_rsrc(d.acc, (unsigned)(3 * DD) * 4u);
 #pragma unroll
         for (int q = 0; q < IC; ++q) {
@@ -538,14 +581,14 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const int cell = c * DD + j * D + i;
-                    G_.y0[r][c] = bld1(Mrs, (need_y0 && okc) ? cell * 4 : OOB);
+                    G_.y0[r][c] = heun ? bld1c(Mrs, (ny0 && okc) ? cell * 4 : OOB)
+                                       : bld1(Mrs, (ny0 && okc) ? cell * 4 : OOB);
                     G_.ac[r][c] = bld1c(Ars, (need_acc && okc) ? cell * 4 : OOB);
                 }
             }
         }
     };
     auto cell_update = [&](int b, int s, long long n, float* Yn) {
-        const bool sample = SERIES && s == 0 && n % a.every == 0;
 #pragma unroll
         for (int q = 0; q < IC; ++q) {
             int uu, i;
@@ -570,7 +613,8 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             const float2 hz2 = BUF(2, uu)[padb(i)];
             float nxt[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
             float3 wn[2];
-            if (mode == MODE_HEUN && (in_disk(j0, i, D) || (j0 + 1 < D && in_disk(j0 + 1, i, D))))
+            // the predictor draws the step's noise; the corrector reuses it (stored in aux)
+            if (mode == MODE_HEUN && s == 0 && (in_disk(j0, i, D) || (j0 + 1 < D && in_disk(j0 + 1, i, D))))
                 thermal_normals_pair(a.seed, step0 + (unsigned long long)n, (unsigned long long)(p * D + i),
                                      (unsigned long long)(a.replica0 + d.k), wn[0], wn[1]);
 #pragma unroll
@@ -603,20 +647,6 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                 const float bx = (col[r][0] + col[r + 2][0] + lft[r][0] + rgt[r][0]) + cf * (hxf + Hx);
                 const float by = (col[r][1] + col[r + 2][1] + lft[r][1] + rgt[r][1]) + cf * (hyf + Hy);
                 const float bz = (col[r][2] + col[r + 2][2] + lft[r][2] + rgt[r][2]) + cf * (hzf + Hz);
-                if (sample && in) {
-                    // m and the energy density -1/2 m.b_ex - c (h + H/2).m of the step's start state
-                    const double mxd = mx, myd = my, mzd = mz;
-                    double e3[3];
-#pragma unroll
-                    for (int c = 0; c < 3; ++c)
-                        e3[c] = (double)col[r][c] + (double)col[r + 2][c] + (double)lft[r][c] + (double)rgt[r][c];
-                    sm[0] += mxd;
-                    sm[1] += myd;
-                    sm[2] += mzd;
-                    sm[3] += -0.5 * (mxd * e3[0] + myd * e3[1] + mzd * e3[2]) -
-                             pr.c_d * (mxd * (hxd + 0.5 * (double)Hx) + myd * (hyd + 0.5 * (double)Hy) +
-                                       mzd * (hzd + 0.5 * (double)Hz));
-                }
                 float nx = 0.f, ny = 0.f, nzv = 0.f;
                 if (mode == MODE_RHS || mode == MODE_RK4) {
                     // f = m x b - alpha m x (m x b)
@@ -674,7 +704,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                         rs[4 * DD] = Hy;
                         rs[5 * DD] = Hz;
                     }
-                    const float3 w = wn[r];
+                    const float3 w = s == 0 ? wn[r] : make_float3(y0[r][0], y0[r][1], y0[r][2]);
                     const float sg = pr.sigma;
                     const float gx = bx * dt + sg * w.x, gy = by * dt + sg * w.y, gz = bz * dt + sg * w.z;
                     const float px = my * gz - mz * gy, py = mz * gx - mx * gz, pz = mx * gy - my * gx;
@@ -682,16 +712,21 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                     const float dy = py - al * (mz * px - mx * pz);
                     const float dz = pz - al * (mx * py - my * px);
                     if (s == 0) {
-                        gbl(d.acc)[cell] = dx;
-                        gbl(d.acc)[DD + cell] = dy;
-                        gbl(d.acc)[2 * DD + cell] = dz;
+                        // predictor m~ = m + Delta_1; keep m + Delta_1/2 and the noise for the corrector
+                        gbl(d.acc)[cell] = mx + 0.5f * dx;
+                        gbl(d.acc)[DD + cell] = my + 0.5f * dy;
+                        gbl(d.acc)[2 * DD + cell] = mz + 0.5f * dz;
+                        gbl(d.aux)[cell] = w.x;
+                        gbl(d.aux)[DD + cell] = w.y;
+                        gbl(d.aux)[2 * DD + cell] = w.z;
                         nx = mx + dx;
                         ny = my + dy;
                         nzv = mz + dz;
                     } else {
-                        nx = y0[r][0] + 0.5f * (ac[r][0] + dx);
-                        ny = y0[r][1] + 0.5f * (ac[r][1] + dy);
-                        nzv = y0[r][2] + 0.5f * (ac[r][2] + dz);
+                        // corrector m' = m + (Delta_1 + Delta_2)/2
+                        nx = ac[r][0] + 0.5f * dx;
+                        ny = ac[r][1] + 0.5f * dy;
+                        nzv = ac[r][2] + 0.5f * dz;
                         if (pr.renorm) {
                             const float rn = 1.0f / sqrtf(nx * nx + ny * ny + nzv * nzv);
                             nx *= rn;
@@ -1266,7 +1301,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         // start state and accumulator are loaded at the top of the iteration
         // (iterations touch disjoint rows of the spectra and of the states they
         // write; a load past the last iteration reads zeros or unused rows)
-        auto row_pass = [&](int s, long long n, const float* Ys, float* Yn, bool fwd) {
+        auto row_pass = [&](int s, long long n, const float* Ys, float* Yn, bool fwd, bool sample) {
             if (g >= n_rb) return;
             float hv[IH];
             SRow sv[IS];
@@ -1276,6 +1311,8 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                 gather(b, s);
                 halo_store(hv);
                 row_unpack_inverse(sv);
+                if constexpr (SERIES)
+                    if (sample) sample_pass(b);
                 cell_update(b, s, n, Yn);
                 halo_load(b + G, Ys, hv);
                 row_load(b + G, sv);
@@ -1306,16 +1343,13 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                         Ys = (s == 0) ? m : d.ya;
                         Yn = (s == 0) ? d.ya : m;
                     }
-                    row_pass(s, n, Ys, Yn, !last);
                     const bool sampled = SERIES && s == 0 && n % a.every == 0;
+                    if (sampled) {
+                        if (tid<OPQ>() < 3 * UG * 4) red4[tid<OPQ>() >> 2][tid<OPQ>() & 3] = 0.0;
+                        __syncthreads();
+                    }
+                    row_pass(s, n, Ys, Yn, !last, sampled);
                     if (sampled) {   // this workgroup's sums of the sample into its partial slots 4..7
-                        __shared__ double red4[3 * MAX_UG][4];
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const double v = wave_sum(sm[q]);
-                            if (lane == 0) red4[wv][q] = v;
-                            sm[q] = 0.0;
-                        }
                         __syncthreads();
                         if (tid<OPQ>() < 4) {
                             const int q = tid<OPQ>();

@@ -180,6 +180,7 @@ struct llg_disk_s {
     CorePart* core_part = nullptr;    // per disk and plaquette-row strip: core-position candidates
     int core_strips = 1;              // strips per disk in core_part
     unsigned plan_modes = 0;          // modes whose co-residency the current plan was checked for
+    unsigned plan_series_modes = 0;   // the same for the series instances of the integrators
     int UG = 1;                       // wavefront groups per workgroup of the persistent launch
     int RSEL = 0;                     // transform policy (radix and column strategy)
     int PMAX = 256;                   // largest FFT size of the handle's disks (kernel instance)
@@ -448,6 +449,7 @@ int plan(llg_disk h, int UG, int RSEL, const int* wg_per_disk, unsigned modes = 
     h->UG = UG;
     h->RSEL = RSEL;
     h->plan_modes = modes;
+    h->plan_series_modes = 0;
     if (!h->desc_dev && (rc = h->dalloc(&h->desc_dev, n))) return rc;
     HIP_TRY(hipMemcpy(h->desc_dev, h->desc.data(), n * sizeof(DiskDesc), hipMemcpyHostToDevice));
     return 0;
@@ -682,8 +684,9 @@ int launch(llg_disk h, int mode, float* m, float* out, long long nsteps, unsigne
             return fail(LLG_EUNSUPPORTED, "the launch plan (" + std::to_string(h->n_wg) +
                                               " workgroups, tuned for the integrator) exceeds what this mode keeps "
                                               "co-resident (" + std::to_string(cap) + "); re-plan with llg_tune");
+        h->plan_modes |= 1u << kmode;   // checked once per plan
     }
-    if (series) {   // the series instance of the integrator: check its own co-residency
+    if (series && !(h->plan_series_modes & (1u << kmode))) {   // the series instance: its own co-residency, once per plan
         const void* k = persistent_kernel(mode, h->UG, h->RSEL, h->PMAX, true);
         if (!k) return fail(LLG_EUNSUPPORTED, "no series kernel instance for this launch shape");
         int dev = 0, ncu = 0, b = 0;
@@ -694,6 +697,7 @@ int launch(llg_disk h, int mode, float* m, float* out, long long nsteps, unsigne
             return fail(LLG_EUNSUPPORTED, "the launch plan (" + std::to_string(h->n_wg) +
                                               " workgroups) exceeds what the series kernel keeps co-resident (" +
                                               std::to_string(ncu * b) + "); re-plan with llg_tune");
+        h->plan_series_modes |= 1u << kmode;
     }
     const int nb = (h->n_bars + 255) / 256;
     hipLaunchKernelGGL(zero_u32, dim3(nb), dim3(256), 0, st, bars_override ? bars_override : h->bars, h->n_bars);
