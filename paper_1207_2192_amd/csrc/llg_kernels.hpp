@@ -495,10 +495,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     // step's start state and the accumulator of the two cells of a column are
     // loaded into registers before the row spectra, so that all of the
     // iteration's loads share one memory latency.
-    // RK4: the step's start state at every stage.  Heun: at the corrector only,
-    // and there the slot carries the noise w stored by the predictor (the
-    // corrector's base m_n + Delta_1/2 comes from the accumulator)
-    auto need_y0 = [&](int s) { return mode == MODE_RK4 || (mode == MODE_HEUN && s == 1); };
+    const bool need_y0 = (mode == MODE_RK4) || (mode == MODE_HEUN);
     // stage record: per step, per stage, (stage state, demag field) of [3][D][D]
     constexpr int NST = (MODE == MODE_HEUN || MODE == MODE_HEUN_VJP) ? 2 : 4;
     float* const recd = a.rec ? a.rec + (size_t)a.nsteps * (2 * NST) * (size_t)d.m_off : nullptr;
@@ -562,9 +559,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     };
     auto gather = [&](int b, int s) {
         const bool need_acc = (mode == MODE_RK4 && s > 0) || (mode == MODE_HEUN && s == 1);
-        const bool heun = mode == MODE_HEUN;
-        const __amdgpu_buffer_rsrc_t Mrs = make_rsrc(heun ? d.aux : m, (unsigned)(3 * DD) * 4u);
-        const bool ny0 = need_y0(s);
+        const __amdgpu_buffer_rsrc_t Mrs = make_rsrc(m, (unsigned)(3 * DD) * 4u);
         const __amdgpu_buffer_rsrc_t Ars = make_rsrc(d.acc, (unsigned)(3 * DD) * 4u);
 #pragma unroll
         for (int q = 0; q < IC; ++q) {
@@ -581,8 +576,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const int cell = c * DD + j * D + i;
-                    G_.y0[r][c] = heun ? bld1c(Mrs, (ny0 && okc) ? cell * 4 : OOB)
-                                       : bld1(Mrs, (ny0 && okc) ? cell * 4 : OOB);
+                    G_.y0[r][c] = bld1(Mrs, (need_y0 && okc) ? cell * 4 : OOB);
                     G_.ac[r][c] = bld1c(Ars, (need_acc && okc) ? cell * 4 : OOB);
                 }
             }
@@ -613,8 +607,8 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             const float2 hz2 = BUF(2, uu)[padb(i)];
             float nxt[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
             float3 wn[2];
-            // the predictor draws the step's noise; the corrector reuses it (stored in aux)
-            if (mode == MODE_HEUN && s == 0 && (in_disk(j0, i, D) || (j0 + 1 < D && in_disk(j0 + 1, i, D))))
+            // both Heun stages draw the step's noise from the same counters
+            if (mode == MODE_HEUN && (in_disk(j0, i, D) || (j0 + 1 < D && in_disk(j0 + 1, i, D))))
                 thermal_normals_pair(a.seed, step0 + (unsigned long long)n, (unsigned long long)(p * D + i),
                                      (unsigned long long)(a.replica0 + d.k), wn[0], wn[1]);
 #pragma unroll
@@ -704,7 +698,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                         rs[4 * DD] = Hy;
                         rs[5 * DD] = Hz;
                     }
-                    const float3 w = s == 0 ? wn[r] : make_float3(y0[r][0], y0[r][1], y0[r][2]);
+                    const float3 w = wn[r];
                     const float sg = pr.sigma;
                     const float gx = bx * dt + sg * w.x, gy = by * dt + sg * w.y, gz = bz * dt + sg * w.z;
                     const float px = my * gz - mz * gy, py = mz * gx - mx * gz, pz = mx * gy - my * gx;
@@ -712,21 +706,18 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                     const float dy = py - al * (mz * px - mx * pz);
                     const float dz = pz - al * (mx * py - my * px);
                     if (s == 0) {
-                        // predictor m~ = m + Delta_1; keep m + Delta_1/2 and the noise for the corrector
-                        gbl(d.acc)[cell] = mx + 0.5f * dx;
-                        gbl(d.acc)[DD + cell] = my + 0.5f * dy;
-                        gbl(d.acc)[2 * DD + cell] = mz + 0.5f * dz;
-                        gbl(d.aux)[cell] = w.x;
-                        gbl(d.aux)[DD + cell] = w.y;
-                        gbl(d.aux)[2 * DD + cell] = w.z;
+                        // predictor m~ = m + Delta_1; Delta_1 kept for the corrector
+                        gbl(d.acc)[cell] = dx;
+                        gbl(d.acc)[DD + cell] = dy;
+                        gbl(d.acc)[2 * DD + cell] = dz;
                         nx = mx + dx;
                         ny = my + dy;
                         nzv = mz + dz;
                     } else {
                         // corrector m' = m + (Delta_1 + Delta_2)/2
-                        nx = ac[r][0] + 0.5f * dx;
-                        ny = ac[r][1] + 0.5f * dy;
-                        nzv = ac[r][2] + 0.5f * dz;
+                        nx = y0[r][0] + 0.5f * (ac[r][0] + dx);
+                        ny = y0[r][1] + 0.5f * (ac[r][1] + dy);
+                        nzv = y0[r][2] + 0.5f * (ac[r][2] + dz);
                         if (pr.renorm) {
                             const float rn = 1.0f / sqrtf(nx * nx + ny * ny + nzv * nzv);
                             nx *= rn;
