@@ -142,11 +142,31 @@ int llg_disk_workgroups(llg_disk h, int k);
  * schedule. */
 int llg_tune(llg_disk h, int unit_groups, int radix_policy, const int* wg_per_disk);
 
+/* Spectra on chip (the small-disk plan of the ragged batch): every disk of h
+ * with FFT size P <= max_P (64 or 128; 0 = none) is stepped by one workgroup
+ * that keeps the disk's row/column spectra (3 (P/2+1) D' complex floats, D'
+ * = D rounded up to 8: 25 KB at P = 64, up to 100 KB at P = 128) in its LDS
+ * for the whole launch of the field kernel and the integrators, so the two
+ * transform phases of a field evaluation exchange them without leaving the
+ * CU; the adjoint and relaxation kernels keep them in global memory, as every
+ * disk of a larger P does.  Every workgroup of those launches reserves the
+ * largest on-chip workspace of the handle.  Re-plans like llg_tune with the
+ * current unit groups and transform policy and the library's workgroup counts
+ * (host; synchronises the device); llg_tune and llg_autotune keep the setting.
+ * Fails with LLG_EUNSUPPORTED, leaving the previous plan, when no workgroup of
+ * the current shape fits a CU with that workspace (use fewer unit groups).
+ * Results are bitwise those of the same plan with the spectra in global
+ * memory.  llg_get_on_chip returns the current max_P. */
+int llg_set_on_chip(llg_disk h, int max_P);
+int llg_get_on_chip(llg_disk h);
+
 /* Autotuner: times llg_rk4_step (integrator 0) or llg_heun_step (1) for
  * probe_steps steps on a private copy of m (device) under every candidate plan
  * (unit groups 1/2/4 x transform policy 0..3 x the library's workgroup counts
- * scaled by 1, 1/2, 1/4) and keeps the fastest.  *best_us (host) receives its
- * time per step in microseconds.  Synchronises; m is not modified. */
+ * scaled by 1, 1/2, 1/4 x spectra on chip off / for P <= 64 / for P <= 128,
+ * the last two where the handle has such disks) and keeps the fastest.
+ * *best_us (host) receives its time per step in microseconds.  Synchronises;
+ * m is not modified. */
 int llg_autotune(llg_disk h, const float* m, const llg_params* p, int integrator, long long probe_steps,
                  void* stream, double* best_us);
 

@@ -36,6 +36,8 @@ SIGNATURES = {
     "llg_tune": (c_int, [c_vp, c_int, c_int, P_int]),
     "llg_autotune": (c_int, [c_vp, c_vp, ctypes.POINTER(LLGParamsC), c_int, c_ll, c_vp, P_double]),
     "llg_launch_shape": (c_int, [c_vp, P_int, P_int, P_int, P_int]),
+    "llg_set_on_chip": (c_int, [c_vp, c_int]),
+    "llg_get_on_chip": (c_int, [c_vp]),
     "llg_demag_field": (c_int, [c_vp, c_vp, c_vp, c_vp]),
     "llg_rhs": (c_int, [c_vp, c_vp, c_vp, ctypes.POINTER(LLGParamsC), c_vp]),
     "llg_rk4_step": (c_int, [c_vp, c_vp, c_ll, ctypes.POINTER(LLGParamsC), c_vp]),

@@ -126,6 +126,18 @@ class Disk:
         self.workgroups = [lib.llg_disk_workgroups(self._h, k) for k in range(self.n)]
         return best.value
 
+    def set_on_chip(self, max_P: int):
+        """Disks with FFT size P <= max_P (64 or 128; 0 = none) run on one workgroup
+        each with their spectra in LDS (llg_set_on_chip); re-plans the launch."""
+        lib = _lib.load()
+        check(lib.llg_set_on_chip(self._h, int(max_P)), "llg_set_on_chip")
+        self.workgroups = [lib.llg_disk_workgroups(self._h, k) for k in range(self.n)]
+
+    @property
+    def on_chip(self) -> int:
+        """The max_P of the on-chip spectra plan (0: none)."""
+        return _lib.load().llg_get_on_chip(self._h)
+
     def launch_shape(self):
         """(unit groups, workgroups, threads per workgroup, transform policy)."""
         ug, nwg, nt, rs = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()

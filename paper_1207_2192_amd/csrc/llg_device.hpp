@@ -23,6 +23,7 @@ constexpr int SB = 8;
 struct DiskDesc {
     int D, P, H, Dp;          // box, FFT size, P/2+1, D rounded up to a multiple of SB
     int n_pairs, G, n_cells, k;  // row pairs, workgroups, masked cells, index in the batch
+    int onchip;               // nonzero: G = 1 and the field kernel and integrators keep the spectra in LDS
     long long m_off;          // float offset of this disk in a packed state
     float* ya;                // stage state A  [3][D][D]
     float* yb;                // stage state B  [3][D][D]
@@ -107,6 +108,11 @@ enum Mode : int {
 };
 
 constexpr int PART_STRIDE = 8;  // doubles of per-workgroup partial sums
+
+// Modes whose kernel instances can keep a small disk's spectra in LDS (the
+// field kernel and the integrators); the adjoint and relaxation kernels always
+// use the workspace in global memory, which every disk keeps.
+constexpr bool on_chip_mode(int mode) { return mode == MODE_DEMAG || mode == MODE_RK4 || mode == MODE_HEUN; }
 
 enum ErrBits : int { ERR_BARRIER = 1, ERR_NONFINITE = 2 };
 

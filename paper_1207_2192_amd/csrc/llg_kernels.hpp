@@ -17,7 +17,11 @@
 //
 // The row spectra live in a [3][Dp/SB][P/2+1][SB] complex workspace per disk
 // (blocks of SB rows, one 64-byte segment per spectral column and block), so a
-// field evaluation moves them through L2/HBM twice per phase pair.
+// field evaluation moves them through L2/HBM twice per phase pair.  A disk of
+// FFT size 64 or 128 that one workgroup steps alone can instead keep that
+// workspace in the workgroup's LDS for the whole launch (ONCHIP): the two
+// phases then exchange the spectra without leaving the CU, and the disk's
+// barriers are workgroup barriers.
 #pragma once
 #include "llg_device.hpp"
 
@@ -42,9 +46,9 @@ struct RowTile {
     static constexpr int floats = 3 * HR * HW;
 };
 
-template <int P, int R, int UG, int MODE, bool LARGE, bool SLOT, bool SER>
+template <int P, int R, int UG, int MODE, bool LARGE, bool SLOT, bool SER, bool ONCHIP>
 __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, const DiskPrm& pr, int g,
-                                         float2* lds, float2* ltw, float* halo) {
+                                         float2* lds, float2* ltw, float* halo, float2* sdyn) {
     constexpr int Tf = P / R;
     constexpr int U = UG * (64 / Tf);          // transforms per component in flight per workgroup
     // the adjoint keeps many values per cell in registers, the P = 512 kernels (LARGE) run
@@ -82,7 +86,42 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     const unsigned char* __restrict__ mask = d.mask;
     float2* __restrict__ S = d.S;
     const int NJB = Dp >> 3;
-    const __amdgpu_buffer_rsrc_t Srs = make_rsrc(S, (unsigned)(3 * H * Dp) * 8u);
+    const unsigned s_bytes = (unsigned)(3 * H * Dp) * 8u;
+    const __amdgpu_buffer_rsrc_t Srs = make_rsrc(S, s_bytes);
+    // spectra accesses by byte offset: buffer instructions on the workspace in
+    // global memory, or LDS (sdyn) for an on-chip disk; an offset out of range
+    // (OOB) reads zero and drops the store in both
+    auto sld2 = [&](int off) -> float2 {
+        if constexpr (ONCHIP)
+            return (unsigned)off < s_bytes ? sdyn[off >> 3] : make_float2(0.f, 0.f);
+        else
+            return bld2(Srs, off);
+    };
+    auto sld4 = [&](int off) -> float4 {
+        if constexpr (ONCHIP)
+            return (unsigned)off < s_bytes ? reinterpret_cast<const float4*>(sdyn)[off >> 4]
+                                           : make_float4(0.f, 0.f, 0.f, 0.f);
+        else
+            return bld4(Srs, off);
+    };
+    auto sst2 = [&](int off, float2 v) {
+        if constexpr (ONCHIP) {
+            if ((unsigned)off < s_bytes) sdyn[off >> 3] = v;
+        } else {
+            bst2(Srs, off, v);
+        }
+    };
+    auto sst4 = [&](int off, float4 v) {
+        if constexpr (ONCHIP) {
+            if ((unsigned)off < s_bytes) reinterpret_cast<float4*>(sdyn)[off >> 4] = v;
+        } else {
+            bst4(Srs, off, v);
+        }
+    };
+    if constexpr (ONCHIP) {   // rows no pass writes read as zeros, as in the cleared workspace
+        for (int i = tid<OPQ>(); i < 3 * H * Dp; i += NT) sdyn[i] = make_float2(0.f, 0.f);
+        __syncthreads();
+    }
     const __amdgpu_buffer_rsrc_t Krs = make_rsrc(d.spec, (unsigned)(4 * H * H) * 4u);
     // byte offset of the spectrum of component c, column k, row j
     auto soff = [&](int c, int k, int j) { return ((((c * NJB + (j >> 3)) * H + k) << 3) + (j & 7)) * 8; };
@@ -156,9 +195,9 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                                           0.5f * (A1.y + B1.y), -0.5f * (A1.x - B1.x));
             const float4 sz = make_float4(0.5f * (A2.x + B2.x), 0.5f * (A2.y - B2.y),
                                           0.5f * (A2.y + B2.y), -0.5f * (A2.x - B2.x));
-            bst4(Srs, soff(0, k, j0), sx);
-            bst4(Srs, soff(1, k, j0), sy);
-            bst4(Srs, soff(2, k, j0), sz);
+            sst4(soff(0, k, j0), sx);
+            sst4(soff(1, k, j0), sy);
+            sst4(soff(2, k, j0), sz);
         }
         __syncthreads();
     };
@@ -195,14 +234,14 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
 #pragma unroll
             for (int j = 0; j < R / 2; ++j) {
                 const int i = t + j * Tf;
-                bst2(Srs, (valid && i < D) ? soff(c, kx, i) : OOB, v[j]);
+                sst2((valid && i < D) ? soff(c, kx, i) : OOB, v[j]);
             }
         } else {
             fft_run<P, R, true, false, false, false, true>(v, mybuf, ltw, t, &stw);
 #pragma unroll
             for (int j = 0; j < R / 2; ++j) {
                 const int i = t + j * Tf;
-                bst2(Srs, (valid && i < D) ? soff(c, kx, i) : OOB, mybuf[padb(i)]);
+                sst2((valid && i < D) ? soff(c, kx, i) : OOB, mybuf[padb(i)]);
             }
             wave_sync();
         }
@@ -218,14 +257,14 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
 #pragma unroll
             for (int j = 0; j < R / 2; ++j) {
                 const int i = t + j * Tf;
-                Z[j] = bld2(Srs, (valid && i < D) ? soff(2, kx, i) : OOB);
+                Z[j] = sld2((valid && i < D) ? soff(2, kx, i) : OOB);
             }
 #pragma unroll
             for (int j = 0; j < R / 2; ++j) {
                 const int i = t + j * Tf;
                 const bool ok = valid && i < D;
-                X[j] = bld2(Srs, ok ? soff(0, kx, i) : OOB);
-                Y[j] = bld2(Srs, ok ? soff(1, kx, i) : OOB);
+                X[j] = sld2(ok ? soff(0, kx, i) : OOB);
+                Y[j] = sld2(ok ? soff(1, kx, i) : OOB);
             }
             // kernel spectra at this lane's points: quarter-plane planes 0 = xx, 1 = yy, 2 = xy, 3 = zz
             auto kidx = [&](int j) {
@@ -277,7 +316,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
 #pragma unroll
         for (int j = 0; j < R / 2; ++j) {   // rows at or past P/2 (>= D) are zero
             const int i = t + j * Tf;
-            c.v[j] = bld2(Srs, (valid && i < D) ? soff(wave, kx, i) : OOB);
+            c.v[j] = sld2((valid && i < D) ? soff(wave, kx, i) : OOB);
         }
     };
     auto col_load_k = [&](int b, ColK& c) {
@@ -320,14 +359,14 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
 #pragma unroll
             for (int j = 0; j < R / 2; ++j) {
                 const int i = t + j * Tf;
-                bst2(Srs, (valid && i < D) ? soff(wave, kx, i) : OOB, v[j]);
+                sst2((valid && i < D) ? soff(wave, kx, i) : OOB, v[j]);
             }
         } else {
             fft_run<P, R, true, false, true, false, true>(v, mybuf, ltw, t);
 #pragma unroll
             for (int j = 0; j < R / 2; ++j) {
                 const int i = t + j * Tf;
-                bst2(Srs, (valid && i < D) ? soff(wave, kx, i) : OOB, mybuf[padb(i)]);
+                sst2((valid && i < D) ? soff(wave, kx, i) : OOB, mybuf[padb(i)]);
             }
         }
     };
@@ -373,9 +412,9 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             const int p = b * U + uu;
             const bool ok = idx < U * H && p < d.n_pairs;
             const int j0 = 2 * p;
-            sv[q].x = bld4(Srs, ok ? soff(0, k, j0) : OOB);
-            sv[q].y = bld4(Srs, ok ? soff(1, k, j0) : OOB);
-            sv[q].z = bld4(Srs, ok ? soff(2, k, j0) : OOB);
+            sv[q].x = sld4(ok ? soff(0, k, j0) : OOB);
+            sv[q].y = sld4(ok ? soff(1, k, j0) : OOB);
+            sv[q].z = sld4(ok ? soff(2, k, j0) : OOB);
         }
     };
     auto row_unpack_inverse = [&](const SRow (&sv)[IS]) {
@@ -1404,6 +1443,8 @@ void llg_persistent(KArgs a) {
     __shared__ float2 lds[LDS_FFT * UG];
     __shared__ float2 ltw[MAX_P];
     __shared__ float halo[halo_floats<UG, POL>(PMAX)];
+    extern __shared__ float4 sdyn4[];   // on-chip spectra (launch-time size; empty when no disk is on chip)
+    float2* const sdyn = reinterpret_cast<float2*>(sdyn4);
     const int wg = blockIdx.x;
     const int di = a.wg2disk[wg];
     if (di < 0) return;
@@ -1411,12 +1452,26 @@ void llg_persistent(KArgs a) {
     const DiskDesc d = a.disks[di];
     const DiskPrm pr = a.prm[di];
     constexpr bool L = PMAX >= 512, SL = column_slots(POL, MODE);
+    constexpr bool OC = on_chip_mode(MODE);
     switch (d.P) {
-        case 64: run_disk<64, Radix<64, POL>::value, UG, MODE, L, SL, SER>(a, d, pr, g, lds, ltw, halo); break;
-        case 128: run_disk<128, Radix<128, POL>::value, UG, MODE, L, SL, SER>(a, d, pr, g, lds, ltw, halo); break;
-        case 256: run_disk<256, Radix<256, POL>::value, UG, MODE, L, SL, SER>(a, d, pr, g, lds, ltw, halo); break;
+        case 64:
+            if (OC && d.onchip)
+                run_disk<64, Radix<64, POL>::value, UG, MODE, L, SL, SER, OC>(a, d, pr, g, lds, ltw, halo, sdyn);
+            else
+                run_disk<64, Radix<64, POL>::value, UG, MODE, L, SL, SER, false>(a, d, pr, g, lds, ltw, halo, sdyn);
+            break;
+        case 128:
+            if (OC && d.onchip)
+                run_disk<128, Radix<128, POL>::value, UG, MODE, L, SL, SER, OC>(a, d, pr, g, lds, ltw, halo, sdyn);
+            else
+                run_disk<128, Radix<128, POL>::value, UG, MODE, L, SL, SER, false>(a, d, pr, g, lds, ltw, halo, sdyn);
+            break;
+        case 256:
+            run_disk<256, Radix<256, POL>::value, UG, MODE, L, SL, SER, false>(a, d, pr, g, lds, ltw, halo, sdyn);
+            break;
         case 512:
-            if constexpr (PMAX >= 512) run_disk<512, Radix<512, POL>::value, UG, MODE, L, SL, SER>(a, d, pr, g, lds, ltw, halo);
+            if constexpr (PMAX >= 512)
+                run_disk<512, Radix<512, POL>::value, UG, MODE, L, SL, SER, false>(a, d, pr, g, lds, ltw, halo, sdyn);
             break;
         default: break;
     }

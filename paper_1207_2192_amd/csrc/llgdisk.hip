@@ -184,6 +184,8 @@ struct llg_disk_s {
     int UG = 1;                       // wavefront groups per workgroup of the persistent launch
     int RSEL = 0;                     // transform policy (radix and column strategy)
     int PMAX = 256;                   // largest FFT size of the handle's disks (kernel instance)
+    int onchip_pmax = 0;              // disks with P <= this (64 or 128; 0: none) run on one workgroup, spectra in LDS
+    unsigned onchip_lds = 0;          // dynamic LDS bytes of the on-chip capable launches (largest on-chip workspace)
     std::vector<DiskDesc> desc;       // host copy of the descriptors
 
     ~llg_disk_s() {
@@ -256,9 +258,24 @@ const void* persistent_kernel(int mode, int UG, int RSEL, int PMAX, bool series 
 constexpr unsigned ALL_MODES = (1u << MODE_DEMAG) | (1u << MODE_RK4) | (1u << MODE_HEUN) | (1u << MODE_RK4_VJP) |
                                (1u << MODE_HEUN_VJP) | (1u << MODE_RELAX);
 
+// Largest on-chip spectra workspace: P = 128, D' = 64 (3 x 65 x 64 complex floats).
+constexpr unsigned MAX_ONCHIP_LDS = 3u * 65u * 64u * 8u;
+
+// Declare the largest dynamic LDS request of a kernel (the on-chip spectra of
+// any handle, so that handles of different sizes never lower it for each
+// other) before its occupancy query and launch.  A size the device cannot hold
+// shows up as zero resident workgroups in the occupancy query, so the call's
+// own status is not needed.
+void allow_dynamic_lds(const void* k) {
+    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)MAX_ONCHIP_LDS);
+    (void)hipGetLastError();
+}
+
 // Workgroups of the given shape that the kernels of every mode in `modes` (bit
-// mask) can keep co-resident.
-int max_coresident_workgroups(int UG, int RSEL, int PMAX, int* out, unsigned modes = ALL_MODES) {
+// mask) can keep co-resident; the field and integrator kernels carry
+// `onchip_lds` bytes of dynamic LDS (the spectra of on-chip disks).
+int max_coresident_workgroups(int UG, int RSEL, int PMAX, int* out, unsigned modes = ALL_MODES,
+                              unsigned onchip_lds = 0) {
     int dev = 0, ncu = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -268,7 +285,9 @@ int max_coresident_workgroups(int UG, int RSEL, int PMAX, int* out, unsigned mod
         const void* k = persistent_kernel(mode, UG, RSEL, PMAX);
         if (!k) return fail(LLG_EUNSUPPORTED, "no kernel instance for this launch shape");
         int b = 0;
-        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k, WG_THREADS * UG, 0));
+        const unsigned dyn = on_chip_mode(mode) ? onchip_lds : 0;
+        if (dyn) allow_dynamic_lds(k);
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k, WG_THREADS * UG, dyn));
         per_cu = std::min(per_cu, b);
     }
     *out = ncu * per_cu;
@@ -309,14 +328,23 @@ int default_unit_groups(llg_disk) {
 // barriers (2500 in the same units: the measured ratio of a barrier to a
 // single-transform P = 256 column iteration); the smallest target T whose
 // per-disk counts (the fewest workgroups that meet T) fit the budget is found
-// by bisection.
+// by bisection.  Disks on chip (P <= h->onchip_pmax) take one workgroup each.
 int plan(llg_disk h, int UG, int RSEL, const int* wg_per_disk, unsigned modes = ALL_MODES, double scale = 1.0) {
     if (UG != 1 && UG != 2 && UG != 4) return fail(LLG_EINVAL, "unit groups must be 1, 2 or 4");
     if (RSEL < 0 || RSEL > 3) return fail(LLG_EINVAL, "transform policy must be 0, 1, 2 or 3");
     const int n = h->n;
+    std::vector<char> oc(n, 0);
+    unsigned oc_lds = 0;
+    for (int k = 0; k < n; ++k) {
+        oc[k] = h->onchip_pmax > 0 && h->P[k] <= h->onchip_pmax;
+        if (oc[k]) oc_lds = std::max(oc_lds, (unsigned)(3 * (h->P[k] / 2 + 1) * h->desc[k].Dp * sizeof(float2)));
+    }
     int cap = 0;
-    int rc = max_coresident_workgroups(UG, RSEL, h->PMAX, &cap, modes);
+    int rc = max_coresident_workgroups(UG, RSEL, h->PMAX, &cap, modes, oc_lds);
     if (rc) return rc;
+    if (cap <= 0)
+        return fail(LLG_EUNSUPPORTED, "no workgroup of " + std::to_string(WG_THREADS * UG) + " threads fits a CU with " +
+                                          std::to_string(oc_lds) + " bytes of on-chip spectra");
     std::vector<int> useful(n), G(n), ncb(n), nrb(n);
     std::vector<double> work(n), iter(n);
     for (int k = 0; k < n; ++k) {
@@ -336,6 +364,7 @@ int plan(llg_disk h, int UG, int RSEL, const int* wg_per_disk, unsigned modes = 
     };
     // fewest workgroups for disk k that meet the target T (or all useful ones)
     auto g_for = [&](int k, double T) {
+        if (oc[k]) return 1;
         int g = 1;
         while (g < useful[k] && stage_time(k, g) > T) ++g;
         return g;
@@ -343,7 +372,7 @@ int plan(llg_disk h, int UG, int RSEL, const int* wg_per_disk, unsigned modes = 
     if (wg_per_disk) {
         for (int k = 0; k < n; ++k) {
             if (wg_per_disk[k] < 1) return fail(LLG_EINVAL, "wg_per_disk must be >= 1");
-            G[k] = std::min(wg_per_disk[k], useful[k]);
+            G[k] = oc[k] ? 1 : std::min(wg_per_disk[k], useful[k]);
         }
     } else {
         if (!(scale > 0.0 && scale <= 1.0)) return fail(LLG_EINVAL, "plan scale must be in (0, 1]");
@@ -444,7 +473,9 @@ int plan(llg_disk h, int UG, int RSEL, const int* wg_per_disk, unsigned modes = 
         d.part = nullptr;
         if ((rc = h->dalloc(&d.part, (size_t)PART_STRIDE * G[k]))) return rc;
         d.G = G[k];
+        d.onchip = oc[k];
     }
+    h->onchip_lds = oc_lds;
     h->G = G;
     h->UG = UG;
     h->RSEL = RSEL;
@@ -676,9 +707,10 @@ int launch(llg_disk h, int mode, float* m, float* out, long long nsteps, unsigne
            const DiskDesc* desc_override = nullptr, unsigned int* bars_override = nullptr,
            double* series = nullptr, long long every = 0) {
     const int kmode = (mode == MODE_RHS || mode == MODE_ENERGY) ? MODE_DEMAG : mode;   // kernel of the mode
+    const unsigned dyn = on_chip_mode(kmode) ? h->onchip_lds : 0;   // on-chip spectra
     if (!(h->plan_modes & (1u << kmode))) {
         int cap = 0;
-        int rc = max_coresident_workgroups(h->UG, h->RSEL, h->PMAX, &cap, 1u << kmode);
+        int rc = max_coresident_workgroups(h->UG, h->RSEL, h->PMAX, &cap, 1u << kmode, h->onchip_lds);
         if (rc) return rc;
         if (h->n_wg > cap)
             return fail(LLG_EUNSUPPORTED, "the launch plan (" + std::to_string(h->n_wg) +
@@ -692,7 +724,8 @@ int launch(llg_disk h, int mode, float* m, float* out, long long nsteps, unsigne
         int dev = 0, ncu = 0, b = 0;
         HIP_TRY(hipGetDevice(&dev));
         HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k, WG_THREADS * h->UG, 0));
+        if (dyn) allow_dynamic_lds(k);
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k, WG_THREADS * h->UG, dyn));
         if (h->n_wg > ncu * b)
             return fail(LLG_EUNSUPPORTED, "the launch plan (" + std::to_string(h->n_wg) +
                                               " workgroups) exceeds what the series kernel keeps co-resident (" +
@@ -709,7 +742,7 @@ int launch(llg_disk h, int mode, float* m, float* out, long long nsteps, unsigne
     a.every = (int)every;
     void* args[] = {&a};
     HIP_TRY(hipLaunchCooperativeKernel(persistent_kernel(mode, h->UG, h->RSEL, h->PMAX, series != nullptr),
-                                       dim3(h->n_wg), dim3(WG_THREADS * h->UG), args, 0, st));
+                                       dim3(h->n_wg), dim3(WG_THREADS * h->UG), args, dyn, st));
     if (step_ptr) {
         hipLaunchKernelGGL(advance_u64, dim3(1), dim3(64), 0, st, h->step_dev, (unsigned long long)nsteps);
         HIP_TRY(hipGetLastError());
@@ -842,6 +875,22 @@ int llg_tune(llg_disk h, int unit_groups, int radix_policy, const int* wg_per_di
     return plan(h, unit_groups, radix_policy, wg_per_disk);
 }
 
+int llg_set_on_chip(llg_disk h, int max_P) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (max_P != 0 && max_P != 64 && max_P != 128) return fail(LLG_EINVAL, "max_P must be 0, 64 or 128");
+    HIP_TRY(hipDeviceSynchronize());
+    const int old = h->onchip_pmax;
+    h->onchip_pmax = max_P;
+    if ((rc = plan(h, h->UG, h->RSEL, nullptr))) {
+        h->onchip_pmax = old;   // the previous plan stays in force
+        return rc;
+    }
+    return 0;
+}
+
+int llg_get_on_chip(llg_disk h) { return h ? h->onchip_pmax : fail(LLG_EINVAL, "null handle"); }
+
 int llg_launch_shape(llg_disk h, int* unit_groups, int* workgroups, int* threads, int* radix_policy) {
     if (!h) return fail(LLG_EINVAL, "null handle");
     if (radix_policy) *radix_policy = h->RSEL;
@@ -878,18 +927,24 @@ int llg_autotune(llg_disk h, const float* m, const llg_params* p, int integrator
     const int mode = integrator == 0 ? MODE_RK4 : MODE_HEUN;
     llg_params* pp = const_cast<llg_params*>(p);
     if ((rc = upload_params(h, pp, st))) return rc;
-    // candidate plans: unit groups x transform policy x workgroup scale
-    std::vector<int> base(h->n);
-    struct Cand { int UG, RSEL; double scale; };
+    // candidate plans: unit groups x transform policy x workgroup scale x spectra
+    // on chip (off, and for P <= 64 / P <= 128 where the handle has such disks)
+    const int pmin = *std::min_element(h->P.begin(), h->P.end());
+    std::vector<int> ocs = {0};
+    if (pmin <= 64) ocs.push_back(64);
+    if (pmin <= 128 && std::count_if(h->P.begin(), h->P.end(), [](int P) { return P == 128; }) > 0) ocs.push_back(128);
+    struct Cand { int UG, RSEL; double scale; int oc; };
     std::vector<Cand> cands;
-    for (int ug : {1, 2, 4})
-        for (int rs : {0, 1, 2, 3})
-            for (double sc : {1.0, 0.5, 0.25}) cands.push_back({ug, rs, sc});
+    for (int oc : ocs)
+        for (int ug : {1, 2, 4})
+            for (int rs : {0, 1, 2, 3})
+                for (double sc : {1.0, 0.5, 0.25}) cands.push_back({ug, rs, sc, oc});
     double best = 1e300;
-    Cand bestc{h->UG, h->RSEL, 1.0};
+    Cand bestc{h->UG, h->RSEL, 1.0, h->onchip_pmax};
     for (const Cand& c : cands) {
         // the tuned plan must keep the integrator and the field kernel (observables) co-resident
         const unsigned modes = (1u << mode) | (1u << MODE_DEMAG);
+        h->onchip_pmax = c.oc;
         if ((rc = plan(h, c.UG, c.RSEL, nullptr, modes, c.scale))) continue;
         float ms = 0.f;
         bool ok = true;
@@ -912,6 +967,7 @@ int llg_autotune(llg_disk h, const float* m, const llg_params* p, int integrator
             bestc = c;
         }
     }
+    h->onchip_pmax = bestc.oc;
     if ((rc = plan(h, bestc.UG, bestc.RSEL, nullptr, (1u << mode) | (1u << MODE_DEMAG), bestc.scale))) return rc;
     if (best_us) *best_us = best * 1e3 / (double)probe_steps;
     return 0;
@@ -1195,6 +1251,7 @@ int llg_graph_create(llg_disk h, int integrator, float* m, long long nsteps, con
     kp.func = const_cast<void*>(persistent_kernel(mode, h->UG, h->RSEL, h->PMAX));
     kp.gridDim = dim3(h->n_wg);
     kp.blockDim = dim3(WG_THREADS * h->UG);
+    kp.sharedMemBytes = h->onchip_lds;   // on-chip spectra of the plan (the descriptors' flags)
     kp.kernelParams = pargs;
     HIP_TRY(hipGraphAddKernelNode(&np, g->graph, &nz, 1, &kp));
     hipKernelNodeAttrValue coop{};
