@@ -150,11 +150,13 @@ int llg_tune(llg_disk h, int unit_groups, int radix_policy, const int* wg_per_di
  * transform phases of a field evaluation exchange them without leaving the
  * CU; the adjoint and relaxation kernels keep them in global memory, as every
  * disk of a larger P does.  Every workgroup of those launches reserves the
- * largest on-chip workspace of the handle.  Re-plans like llg_tune with the
- * current unit groups and transform policy and the library's workgroup counts
- * (host; synchronises the device); llg_tune and llg_autotune keep the setting.
- * Fails with LLG_EUNSUPPORTED, leaving the previous plan, when no workgroup of
- * the current shape fits a CU with that workspace (use fewer unit groups).
+ * largest on-chip workspace of the handle.  The on-chip kernel instances have
+ * one group of three wavefronts per workgroup.  Re-plans like llg_tune with
+ * the current unit groups and transform policy and the library's workgroup
+ * counts (host; synchronises the device); llg_tune and llg_autotune keep the
+ * setting.  Fails with LLG_EUNSUPPORTED, leaving the previous plan, when the
+ * current plan has more than one unit group (and so does llg_tune asking for
+ * more than one while a limit is set).
  * Results are bitwise those of the same plan with the spectra in global
  * memory.  llg_get_on_chip returns the current max_P. */
 int llg_set_on_chip(llg_disk h, int max_P);
@@ -163,8 +165,9 @@ int llg_get_on_chip(llg_disk h);
 /* Autotuner: times llg_rk4_step (integrator 0) or llg_heun_step (1) for
  * probe_steps steps on a private copy of m (device) under every candidate plan
  * (unit groups 1/2/4 x transform policy 0..3 x the library's workgroup counts
- * scaled by 1, 1/2, 1/4 x spectra on chip off / for P <= 64 / for P <= 128,
- * the last two where the handle has such disks) and keeps the fastest.
+ * scaled by 1, 1/2, 1/4, with the spectra in global memory; and where the
+ * handle has disks of P <= 64 / P <= 128, those disks on chip with one unit
+ * group, transform policy 0..3 and the full budget) and keeps the fastest.
  * *best_us (host) receives its time per step in microseconds.  Synchronises;
  * m is not modified. */
 int llg_autotune(llg_disk h, const float* m, const llg_params* p, int integrator, long long probe_steps,

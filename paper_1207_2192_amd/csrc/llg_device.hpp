@@ -109,10 +109,14 @@ enum Mode : int {
 
 constexpr int PART_STRIDE = 8;  // doubles of per-workgroup partial sums
 
-// Modes whose kernel instances can keep a small disk's spectra in LDS (the
-// field kernel and the integrators); the adjoint and relaxation kernels always
-// use the workspace in global memory, which every disk keeps.
+// Kernel instances that can keep a small disk's spectra in LDS: the field
+// kernel and the integrators, with one group of three wavefronts per
+// workgroup (wider workgroups would carry the extra code path at a higher
+// register count in every plan, where it is never the faster choice); the
+// adjoint and relaxation kernels always use the workspace in global memory,
+// which every disk keeps.
 constexpr bool on_chip_mode(int mode) { return mode == MODE_DEMAG || mode == MODE_RK4 || mode == MODE_HEUN; }
+constexpr bool on_chip_instance(int mode, int UG) { return on_chip_mode(mode) && UG == 1; }
 
 enum ErrBits : int { ERR_BARRIER = 1, ERR_NONFINITE = 2 };
 

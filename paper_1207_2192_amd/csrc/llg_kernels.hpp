@@ -1452,7 +1452,7 @@ void llg_persistent(KArgs a) {
     const DiskDesc d = a.disks[di];
     const DiskPrm pr = a.prm[di];
     constexpr bool L = PMAX >= 512, SL = column_slots(POL, MODE);
-    constexpr bool OC = on_chip_mode(MODE);
+    constexpr bool OC = on_chip_instance(MODE, UG);
     switch (d.P) {
         case 64:
             if (OC && d.onchip)

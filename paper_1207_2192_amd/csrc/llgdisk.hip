@@ -285,7 +285,7 @@ int max_coresident_workgroups(int UG, int RSEL, int PMAX, int* out, unsigned mod
         const void* k = persistent_kernel(mode, UG, RSEL, PMAX);
         if (!k) return fail(LLG_EUNSUPPORTED, "no kernel instance for this launch shape");
         int b = 0;
-        const unsigned dyn = on_chip_mode(mode) ? onchip_lds : 0;
+        const unsigned dyn = on_chip_instance(mode, UG) ? onchip_lds : 0;
         if (dyn) allow_dynamic_lds(k);
         HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k, WG_THREADS * UG, dyn));
         per_cu = std::min(per_cu, b);
@@ -333,6 +333,8 @@ int plan(llg_disk h, int UG, int RSEL, const int* wg_per_disk, unsigned modes = 
     if (UG != 1 && UG != 2 && UG != 4) return fail(LLG_EINVAL, "unit groups must be 1, 2 or 4");
     if (RSEL < 0 || RSEL > 3) return fail(LLG_EINVAL, "transform policy must be 0, 1, 2 or 3");
     const int n = h->n;
+    if (h->onchip_pmax > 0 && UG != 1)
+        return fail(LLG_EUNSUPPORTED, "spectra on chip need one unit group per workgroup");
     std::vector<char> oc(n, 0);
     unsigned oc_lds = 0;
     for (int k = 0; k < n; ++k) {
@@ -707,7 +709,7 @@ int launch(llg_disk h, int mode, float* m, float* out, long long nsteps, unsigne
            const DiskDesc* desc_override = nullptr, unsigned int* bars_override = nullptr,
            double* series = nullptr, long long every = 0) {
     const int kmode = (mode == MODE_RHS || mode == MODE_ENERGY) ? MODE_DEMAG : mode;   // kernel of the mode
-    const unsigned dyn = on_chip_mode(kmode) ? h->onchip_lds : 0;   // on-chip spectra
+    const unsigned dyn = on_chip_instance(kmode, h->UG) ? h->onchip_lds : 0;   // on-chip spectra
     if (!(h->plan_modes & (1u << kmode))) {
         int cap = 0;
         int rc = max_coresident_workgroups(h->UG, h->RSEL, h->PMAX, &cap, 1u << kmode, h->onchip_lds);
@@ -935,10 +937,11 @@ int llg_autotune(llg_disk h, const float* m, const llg_params* p, int integrator
     if (pmin <= 128 && std::count_if(h->P.begin(), h->P.end(), [](int P) { return P == 128; }) > 0) ocs.push_back(128);
     struct Cand { int UG, RSEL; double scale; int oc; };
     std::vector<Cand> cands;
-    for (int oc : ocs)
-        for (int ug : {1, 2, 4})
-            for (int rs : {0, 1, 2, 3})
-                for (double sc : {1.0, 0.5, 0.25}) cands.push_back({ug, rs, sc, oc});
+    for (int ug : {1, 2, 4})
+        for (int rs : {0, 1, 2, 3})
+            for (double sc : {1.0, 0.5, 0.25}) cands.push_back({ug, rs, sc, 0});
+    for (size_t q = 1; q < ocs.size(); ++q)   // on chip: one unit group, the full workgroup budget
+        for (int rs : {0, 1, 2, 3}) cands.push_back({1, rs, 1.0, ocs[q]});
     double best = 1e300;
     Cand bestc{h->UG, h->RSEL, 1.0, h->onchip_pmax};
     for (const Cand& c : cands) {

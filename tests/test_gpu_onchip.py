@@ -48,10 +48,11 @@ def ragged():
 
 @pytest.mark.parametrize("R,L,P", [(15.0, 5.0, 0), (30.0, 10.0, 0), (31.0, 20.0, 0), (40.0, 7.5, 0),
                                    (61.0, 12.0, 0), (64.0, 10.0, 0), (30.0, 10.0, 128)])
-@pytest.mark.parametrize("ug,pol", [(1, 0), (1, 3), (2, 1), (2, 2)])
-def test_field_rhs_energy_on_chip_match_oracle(R, L, P, ug, pol):
+@pytest.mark.parametrize("pol", [0, 1, 2, 3])
+def test_field_rhs_energy_on_chip_match_oracle(R, L, P, pol):
     from paper_1207_2192_amd import Disk, LLGParams
     disk = Disk.build(R, L, 2.0, P)
+    ug = 1
     disk.tune(ug, None, pol)
     disk.set_on_chip(disk.P[0])
     assert disk.on_chip == disk.P[0] and disk.workgroups == [1]
@@ -234,16 +235,22 @@ def test_bad_on_chip_requests_keep_the_plan():
     p = LLGParams(alpha=0.05, c=C_PY, dtau=0.04)
     ref = m0.clone()
     disk.rk4_step(ref, 3, p)
-    # four groups of three wavefronts per workgroup leave no room for 100 KB of
-    # spectra at P = 128: refused, the previous plan stays in force
+    # on-chip instances have one group of three wavefronts per workgroup: with
+    # four the request is refused and the previous plan stays in force
     disk.tune(4, None, 0)
-    try:
+    with pytest.raises(LLGError):
         disk.set_on_chip(128)
-        refused = False
-    except LLGError:
-        refused = True
-    print("P=128 on chip with four unit groups refused:", refused, flush=True)
-    assert disk.on_chip == (0 if refused else 128)
+    assert disk.on_chip == 0 and disk.launch_shape()[0] == 4
+    m = m0.clone()
+    disk.rk4_step(m, 3, p)
+    disk.check()
+    assert torch.equal(m, ref)
+    # and a wider re-plan while disks are on chip is refused too
+    disk.tune(1, None, 0)
+    disk.set_on_chip(128)
+    with pytest.raises(LLGError):
+        disk.tune(2, None, 0)
+    assert disk.on_chip == 128 and disk.workgroups == [1]
     m = m0.clone()
     disk.rk4_step(m, 3, p)
     disk.check()
