@@ -11,7 +11,14 @@ eq. OG, f_G in GHz for Permalloy; and over the sweep the slope of k_F/L
 against L/R (eq. kFlinear: about 1/4) and of |Omega_G| against kt/(2 pi)
 (unit slope, Fig. nu-v-kFoL).
 
-    python -m experiments.thiele_sweep [--quick]
+The stability scan (--stability) probes the minimum thickness for a stable
+vortex (Fig. f-v-LoR: f_G falls to zero there) over thinner films: the sign of
+the static stiffness from relaxations at 0 and 2a, and the paper's dynamic
+check — a vortex relaxed near half the radius, released with alpha = 0.02,
+must move the way the Thiele equation gives for a restoring force (spiral
+inwards) — reported as the radial drift of the core and whether it is kept.
+
+    python -m experiments.thiele_sweep [--quick] [--stability]
 prints progress lines and one JSON report.
 """
 from __future__ import annotations
@@ -109,12 +116,69 @@ def run(geoms, *, dtau=0.04, tau_damped=1000.0, periods=6.0, max_steps=1_200_000
             "free_steps": n_free, "sample_every": every, "wall_s": time.perf_counter() - t0}
 
 
+def stability_scan(geoms, *, dtau=0.04, tau=4000.0, every=500, start_frac=0.5, log=print):
+    """Per (R, L): the two-point stiffness kt (eq. Ux) of relaxations at 0 and 2a, and
+    the radial drift of a vortex relaxed at (start_frac R, 0) and released with
+    alpha = 0.02 for tau: the least-squares slope of r(t) over the run (nm per unit
+    tau), the first and last core radius, and whether a +1 vortex is still found."""
+    t0 = time.perf_counter()
+    _, lam = material(10.0)
+    n = len(geoms)
+    R_l = [R for R, _ in geoms for _ in (0, 1)]
+    L_l = [L for _, L in geoms for _ in (0, 1)]
+    X_l = [(X, 0.0) for _ in geoms for X in (0.0, 2 * A_NM)]
+    batch, m, out, U, core = relax_batch(R_l, L_l, X_l, lam)
+    batch.close()
+    res = []
+    for g, (R, L) in enumerate(geoms):
+        r1 = math.hypot(core[2 * g + 1, 0], core[2 * g + 1, 1]) / A_NM
+        res.append(dict(R_nm=R, L_nm=L, L_over_R=L / R, kt_two_point=stiffness_two_point(U[2 * g], U[2 * g + 1], r1),
+                        vortex_found_static=bool(core[2 * g, 4] > 0 and core[2 * g + 1, 4] > 0),
+                        relax_residual=float(max(out[2 * g, 3], out[2 * g + 1, 3]))))
+    log(f"# static: {2 * n} relaxations ({time.perf_counter() - t0:.1f} s)")
+    # dynamic check from a vortex relaxed near half the radius
+    starts = [(start_frac * R, 0.0) for R, _ in geoms]
+    batch, m, out, U, core0 = relax_batch([R for R, _ in geoms], [L for _, L in geoms], starts, lam)
+    prm = [LLGParams(alpha=0.02, c=material(L)[0].c, dtau=dtau) for _, L in geoms]
+    nsteps = int(round(tau / dtau)) // every * every
+    t1 = time.perf_counter()
+    t, cores = sample_cores(batch, m, nsteps, every, lambda s0, k: batch.rk4_step(m, k, prm), lam)
+    log(f"# dynamic: {nsteps} damped RK4 steps of {n} disks from r = {start_frac} R "
+        f"({time.perf_counter() - t1:.1f} s)")
+    batch.close()
+    tt = t * dtau
+    for g, r in enumerate(res):
+        found = cores[:, g, 4] > 0
+        rad = np.hypot(cores[:, g, 0], cores[:, g, 1])
+        r["start_radius_nm"] = float(math.hypot(core0[g, 0], core0[g, 1]))
+        r["vortex_kept"] = bool(found.all())
+        if found.sum() >= 2:
+            slope = float(np.polyfit(tt[found], rad[found], 1)[0])
+            r.update(drift_nm_per_tau=slope, end_radius_nm=float(rad[found][-1]))
+        else:
+            r.update(drift_nm_per_tau=None, end_radius_nm=None)
+        r["stable"] = bool(r["kt_two_point"] > 0 and r["vortex_kept"] and (r["drift_nm_per_tau"] or 0.0) < 0.0)
+    return {"geometries": res, "dtau": dtau, "tau": tau, "start_frac": start_frac,
+            "wall_s": time.perf_counter() - t0}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--quick", action="store_true", help="two radii only, shorter runs")
     ap.add_argument("--periods", type=float, default=6.0)
+    ap.add_argument("--stability", action="store_true",
+                    help="scan thinner films (L = 1..5 nm) for the minimum thickness of a stable vortex")
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
+    if args.stability:
+        geoms = [(R, L) for R in RADII for L in (1.0, 2.0, 3.0, 4.0, 5.0)]
+        rep = stability_scan(geoms, log=lambda s: print(s, flush=True))
+        for r in rep["geometries"]:
+            print(f"# R={r['R_nm']:.0f} L={r['L_nm']:.0f}: kt={r['kt_two_point']:.5f} drift={r['drift_nm_per_tau']} "
+                  f"r {r['start_radius_nm']:.1f} -> {r['end_radius_nm']} kept={r['vortex_kept']} "
+                  f"stable={r['stable']}", flush=True)
+        print(json.dumps(rep), flush=True)
+        return rep
     geoms = [(R, L) for R in RADII for L in THICK]
     if args.quick:
         geoms = [(30.0, 10.0), (30.0, 20.0), (60.0, 20.0)]
