@@ -138,6 +138,11 @@ int llg_disk_workgroups(llg_disk h, int k);
  * components of one spectral column, else one wavefront per component; the
  * adjoint and relaxation kernels ignore bit 1), and the number of workgroups
  * per disk (wg_per_disk, host, n entries; NULL = the library's choice).
+ * The plan keeps the kernels of every mode co-resident (the adjoint and
+ * relaxation kernels hold fewer workgroups per CU than the integrators), so
+ * explicit counts are trimmed, largest first, to that limit; llg_autotune
+ * plans for its integrator and the field kernel only, and a mode launched
+ * later under such a plan is checked and refused if it cannot hold the plan.
  * Results do not depend on the plan beyond float rounding of the radix
  * schedule. */
 int llg_tune(llg_disk h, int unit_groups, int radix_policy, const int* wg_per_disk);
