@@ -324,6 +324,15 @@ int llg_heun_vjp(llg_disk h, const float* rec, long long nsteps, unsigned long l
 int llg_core_position_vjp(llg_disk h, const float* m, double lambda_ex_nm, const double* core,
                           const double* rbar, float* mbar, void* stream);
 
+/* Failure-path test hook (host): every later launch of h gives a group-
+ * barrier wait `polls` polls (each a device-coherent load, about a
+ * microsecond) before it records
+ * LLG_EDEVICE "group barrier timed out" for llg_check and leaves the kernel,
+ * as it would after a lost workgroup; 0 restores the default budget of 2^22
+ * polls (seconds).  Graphs keep the budget of their creation.  States written by a
+ * launch that timed out are unspecified. */
+int llg_debug_spin_limit(llg_disk h, unsigned int polls);
+
 /* The noise w that llg_heun_step uses at one time step (test hook), packed
  * like m (zero outside the disks). */
 int llg_noise(llg_disk h, unsigned long long seed, unsigned long long step,

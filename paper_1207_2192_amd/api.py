@@ -133,6 +133,11 @@ class Disk:
         check(lib.llg_set_on_chip(self._h, int(max_P)), "llg_set_on_chip")
         self.workgroups = [lib.llg_disk_workgroups(self._h, k) for k in range(self.n)]
 
+    def debug_spin_limit(self, polls: int):
+        """Failure-path test hook (llg_debug_spin_limit): group-barrier waits of later
+        launches give up after `polls` polls; 0 restores the default."""
+        check(_lib.load().llg_debug_spin_limit(self._h, int(polls)), "llg_debug_spin_limit")
+
     @property
     def on_chip(self) -> int:
         """The max_P of the on-chip spectra plan (0: none)."""

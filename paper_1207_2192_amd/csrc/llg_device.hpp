@@ -144,6 +144,7 @@ struct KArgs {
     // (<m_x>, <m_y>, <m_z>, E) in float64
     double* series;
     int every, n_disks;
+    unsigned int spin_limit;   // polls of a group-barrier wait before it gives up (ERR_BARRIER)
 };
 
 // ---------------------------------------------------------------- Philox4x32-10
@@ -328,9 +329,10 @@ __device__ __forceinline__ int tid() {
 // a launch (it is cleared before each launch); `target` = epoch * G.  A wait
 // that exceeds the spin budget raises ERR_BARRIER and returns false so that
 // every wave leaves the kernel.
-constexpr unsigned int SPIN_LIMIT = 1u << 22;
+constexpr unsigned int SPIN_LIMIT = 1u << 22;   // default budget (seconds of waiting)
 
-__device__ __forceinline__ bool group_barrier(unsigned int* bar, unsigned int target, int G, int* err) {
+__device__ __forceinline__ bool group_barrier(unsigned int* bar, unsigned int target, int G, int* err,
+                                              unsigned int spin_limit) {
     drain_stores();
     __syncthreads();
     if (G == 1) return true;
@@ -341,7 +343,7 @@ __device__ __forceinline__ bool group_barrier(unsigned int* bar, unsigned int ta
         int ok = 1;
         while (__hip_atomic_load(gbl(bar), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(1);
-            if (++spins > SPIN_LIMIT) {
+            if (++spins > spin_limit) {
                 ok = 0;
                 raise_err(err, (int)ERR_BARRIER);
                 break;

@@ -1205,7 +1205,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             load_state_rows(b, m);
             row_forward_store(b);
         }
-        if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
+        if (!group_barrier(d.bar, ++epoch * G, G, a.err, a.spin_limit)) return;
         const double Xc = a.relax_x[2 * d.k], Yc = a.relax_x[2 * d.k + 1];
         double lx = 0.0, ly = 0.0, res = 0.0, Cx = 0.0, Cy = 0.0;
         long long sweep = 0;
@@ -1214,7 +1214,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         __shared__ double red8[3 * MAX_UG][8];
         for (; sweep < a.nsteps; ++sweep) {
             column_pass();
-            if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
+            if (!group_barrier(d.bar, ++epoch * G, G, a.err, a.spin_limit)) return;
             for (int q = 0; q < 8; ++q) rq[q] = 0.0;
             for (int b = g; b < n_rb; b += G) {
                 row_inverse(b);
@@ -1239,7 +1239,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                     st_shd(d.part + g * PART_STRIDE + q, acc);
                 }
             }
-            if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
+            if (!group_barrier(d.bar, ++epoch * G, G, a.err, a.spin_limit)) return;
             // every workgroup of the disk reduces the same partials in the same order
             double t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             for (int gg = 0; gg < G; ++gg)
@@ -1299,9 +1299,9 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                 if (k < K) row_forward_store(b);
             }
             if (k == K) break;
-            if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
+            if (!group_barrier(d.bar, ++epoch * G, G, a.err, a.spin_limit)) return;
             column_pass();
-            if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
+            if (!group_barrier(d.bar, ++epoch * G, G, a.err, a.spin_limit)) return;
         }
         write_partials(e_ex, e_dm, 0.0);
         return;
@@ -1311,7 +1311,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             load_state_rows(b, m);
             row_forward_store(b);
         }
-        if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
+        if (!group_barrier(d.bar, ++epoch * G, G, a.err, a.spin_limit)) return;
 
         // one row iteration of a field evaluation: issue every load, then stage, transform and update
         auto row_step = [&](int b, int s, long long n, const float* Ys, float* Yn) {
@@ -1352,7 +1352,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
 
         if constexpr (MODE == MODE_DEMAG) {
             column_pass();
-            if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
+            if (!group_barrier(d.bar, ++epoch * G, G, a.err, a.spin_limit)) return;
             for (int b = g; b < n_rb; b += G) row_step(b, 0, 0, m, nullptr);
             if (mode == MODE_ENERGY) write_partials(e_ex, e_dm, e_ext);
         } else {
@@ -1360,7 +1360,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             for (long long n = 0; n < a.nsteps; ++n) {
                 for (int s = 0; s < nst; ++s) {
                     column_pass();
-                    if (!group_barrier(d.bar, ++epoch * G, G, a.err)) return;
+                    if (!group_barrier(d.bar, ++epoch * G, G, a.err, a.spin_limit)) return;
                     set_field(pr.tau0 + ((double)n + stage_frac(nst, s)) * pr.dtau_d);
                     const bool last = (n == a.nsteps - 1) && (s == nst - 1);
                     // state whose field is evaluated (Ys) and where the next stage state goes (Yn)
@@ -1388,7 +1388,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                             st_shd(d.part + g * PART_STRIDE + 4 + q, acc);
                         }
                     }
-                    if (!last && !group_barrier(d.bar, ++epoch * G, G, a.err)) return;
+                    if (!last && !group_barrier(d.bar, ++epoch * G, G, a.err, a.spin_limit)) return;
                     // stage 0 is never the last stage: every workgroup's partials of a
                     // sample are visible here; workgroup 0 sums them in workgroup order
                     if (sampled && g == 0 && tid<OPQ>() < 4) {

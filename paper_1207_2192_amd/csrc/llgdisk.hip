@@ -185,6 +185,7 @@ struct llg_disk_s {
     int RSEL = 0;                     // transform policy (radix and column strategy)
     int PMAX = 256;                   // largest FFT size of the handle's disks (kernel instance)
     int onchip_pmax = 0;              // disks with P <= this (64 or 128; 0: none) run on one workgroup, spectra in LDS
+    unsigned spin_limit = SPIN_LIMIT; // polls of a group-barrier wait before it raises ERR_BARRIER
     unsigned onchip_lds = 0;          // dynamic LDS bytes of the on-chip capable launches (largest on-chip workspace)
     std::vector<DiskDesc> desc;       // host copy of the descriptors
 
@@ -699,6 +700,7 @@ KArgs make_args(llg_disk h, const DiskPrm* prm, int mode, float* m, float* out, 
     a.series = nullptr;
     a.every = 0;
     a.n_disks = h->n;
+    a.spin_limit = h->spin_limit;
     return a;
 }
 
@@ -892,6 +894,12 @@ int llg_set_on_chip(llg_disk h, int max_P) {
 }
 
 int llg_get_on_chip(llg_disk h) { return h ? h->onchip_pmax : fail(LLG_EINVAL, "null handle"); }
+
+int llg_debug_spin_limit(llg_disk h, unsigned int polls) {
+    if (!h) return fail(LLG_EINVAL, "null handle");
+    h->spin_limit = polls ? polls : SPIN_LIMIT;
+    return 0;
+}
 
 int llg_launch_shape(llg_disk h, int* unit_groups, int* workgroups, int* threads, int* radix_policy) {
     if (!h) return fail(LLG_EINVAL, "null handle");
