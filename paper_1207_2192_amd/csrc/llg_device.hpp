@@ -27,7 +27,7 @@ struct DiskDesc {
     long long m_off;          // float offset of this disk in a packed state
     float* ya;                // stage state A  [3][D][D]
     float* yb;                // stage state B  [3][D][D]
-    float* acc;               // RK4 accumulator / Heun predictor increment / adjoint accumulator [3][D][D]
+    float* acc;               // RK4 accumulator / Heun m_n + Delta_1/2 / adjoint accumulator [3][D][D]
     float* aux;               // adjoint: direct part of the stage cotangent [3][D][D]
     float2* S;                // row/column spectra [3][Dp/SB][H][SB] (blocks of SB rows)
     const float* spec;        // kernel spectra quarter planes [4][H][H] (xx, yy, xy, zz) / P^2

@@ -534,7 +534,10 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     // step's start state and the accumulator of the two cells of a column are
     // loaded into registers before the row spectra, so that all of the
     // iteration's loads share one memory latency.
-    const bool need_y0 = (mode == MODE_RK4) || (mode == MODE_HEUN);
+    // (RK4: at stage 0 the state being evaluated is the start state itself, so
+    // its values come from the staged rows and only later stages load it;
+    // Heun: the corrector's base m_n + Delta_1/2 is kept in the accumulator)
+    auto need_y0 = [&](int s) { return mode == MODE_RK4 && s > 0; };
     // stage record: per step, per stage, (stage state, demag field) of [3][D][D]
     constexpr int NST = (MODE == MODE_HEUN || MODE == MODE_HEUN_VJP) ? 2 : 4;
     float* const recd = a.rec ? a.rec + (size_t)a.nsteps * (2 * NST) * (size_t)d.m_off : nullptr;
@@ -598,8 +601,11 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     };
     auto gather = [&](int b, int s) {
         const bool need_acc = (mode == MODE_RK4 && s > 0) || (mode == MODE_HEUN && s == 1);
+        const bool ny0 = need_y0(s);
         const __amdgpu_buffer_rsrc_t Mrs = make_rsrc(m, (unsigned)(3 * DD) * 4u);
         const __amdgpu_buffer_rsrc_t Ars = make_rsrc(d.acc, (unsigned)(3 * DD) * 4u);
+        // a stage that needs neither array issues no load at all (the
+        // conditions are uniform); masked elements of a needed one read zero
 #pragma unroll
         for (int q = 0; q < IC; ++q) {
             int uu, i;
@@ -615,8 +621,10 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const int cell = c * DD + j * D + i;
-                    G_.y0[r][c] = bld1(Mrs, (need_y0 && okc) ? cell * 4 : OOB);
-                    G_.ac[r][c] = bld1c(Ars, (need_acc && okc) ? cell * 4 : OOB);
+                    G_.y0[r][c] = 0.f;
+                    G_.ac[r][c] = 0.f;
+                    if (ny0) G_.y0[r][c] = bld1(Mrs, okc ? cell * 4 : OOB);
+                    if (need_acc) G_.ac[r][c] = bld1c(Ars, okc ? cell * 4 : OOB);
                 }
             }
         }
@@ -709,9 +717,9 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                             gbl(d.acc)[DD + cell] = ac[r][1] + w * fy;
                             gbl(d.acc)[2 * DD + cell] = ac[r][2] + w * fz;
                             const float h = (s == 2) ? dt : 0.5f * dt;
-                            nx = y0[r][0] + h * fx;
-                            ny = y0[r][1] + h * fy;
-                            nzv = y0[r][2] + h * fz;
+                            nx = (s == 0 ? mx : y0[r][0]) + h * fx;
+                            ny = (s == 0 ? my : y0[r][1]) + h * fy;
+                            nzv = (s == 0 ? mz : y0[r][2]) + h * fz;
                         } else {
                             const float h6 = dt * (1.0f / 6.0f);
                             nx = y0[r][0] + h6 * (ac[r][0] + fx);
@@ -745,18 +753,18 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                     const float dy = py - al * (mz * px - mx * pz);
                     const float dz = pz - al * (mx * py - my * px);
                     if (s == 0) {
-                        // predictor m~ = m + Delta_1; Delta_1 kept for the corrector
-                        gbl(d.acc)[cell] = dx;
-                        gbl(d.acc)[DD + cell] = dy;
-                        gbl(d.acc)[2 * DD + cell] = dz;
+                        // predictor m~ = m + Delta_1; m + Delta_1/2 kept for the corrector
+                        gbl(d.acc)[cell] = mx + 0.5f * dx;
+                        gbl(d.acc)[DD + cell] = my + 0.5f * dy;
+                        gbl(d.acc)[2 * DD + cell] = mz + 0.5f * dz;
                         nx = mx + dx;
                         ny = my + dy;
                         nzv = mz + dz;
                     } else {
-                        // corrector m' = m + (Delta_1 + Delta_2)/2
-                        nx = y0[r][0] + 0.5f * (ac[r][0] + dx);
-                        ny = y0[r][1] + 0.5f * (ac[r][1] + dy);
-                        nzv = y0[r][2] + 0.5f * (ac[r][2] + dz);
+                        // corrector m' = (m + Delta_1/2) + Delta_2/2
+                        nx = ac[r][0] + 0.5f * dx;
+                        ny = ac[r][1] + 0.5f * dy;
+                        nzv = ac[r][2] + 0.5f * dz;
                         if (pr.renorm) {
                             const float rn = 1.0f / sqrtf(nx * nx + ny * ny + nzv * nzv);
                             nx *= rn;
