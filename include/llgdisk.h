@@ -324,6 +324,18 @@ int llg_heun_vjp(llg_disk h, const float* rec, long long nsteps, unsigned long l
 int llg_core_position_vjp(llg_disk h, const float* m, double lambda_ex_nm, const double* core,
                           const double* rbar, float* mbar, void* stream);
 
+/* Opt-in launch timing (host): with enable set, every later persistent
+ * launch of h (the field kernel, the integrators, their series, adjoint and
+ * relaxation forms; not graph replays) is bracketed by two HIP events on its
+ * stream, just around the cooperative kernel (after the barrier reset), kept
+ * per kind of launch.  llg_last_launch_ms waits for the last launch of one
+ * kind (mode: 0 field, 1 right-hand side, 2 energy, 3 RK4, 4 Heun, 5 RK4
+ * adjoint, 6 relaxation, 7 Heun adjoint) and returns its duration in ms;
+ * LLG_EINVAL when no launch of that kind was timed since timing was
+ * (re-)enabled.  Costs two event records per launch; off by default. */
+int llg_timing(llg_disk h, int enable);
+int llg_last_launch_ms(llg_disk h, int mode, float* ms);
+
 /* Failure-path test hook (host): every later launch of h gives a group-
  * barrier wait `polls` polls (each a device-coherent load, about a
  * microsecond) before it records

@@ -39,6 +39,8 @@ SIGNATURES = {
     "llg_set_on_chip": (c_int, [c_vp, c_int]),
     "llg_get_on_chip": (c_int, [c_vp]),
     "llg_debug_spin_limit": (c_int, [c_vp, ctypes.c_uint]),
+    "llg_timing": (c_int, [c_vp, c_int]),
+    "llg_last_launch_ms": (c_int, [c_vp, c_int, ctypes.POINTER(ctypes.c_float)]),
     "llg_demag_field": (c_int, [c_vp, c_vp, c_vp, c_vp]),
     "llg_rhs": (c_int, [c_vp, c_vp, c_vp, ctypes.POINTER(LLGParamsC), c_vp]),
     "llg_rk4_step": (c_int, [c_vp, c_vp, c_ll, ctypes.POINTER(LLGParamsC), c_vp]),

@@ -133,6 +133,19 @@ class Disk:
         check(lib.llg_set_on_chip(self._h, int(max_P)), "llg_set_on_chip")
         self.workgroups = [lib.llg_disk_workgroups(self._h, k) for k in range(self.n)]
 
+    def timing(self, enable: bool = True):
+        """Opt-in timing of the persistent launches (llg_timing)."""
+        check(_lib.load().llg_timing(self._h, int(bool(enable))), "llg_timing")
+
+    LAUNCH_MODES = {"field": 0, "rhs": 1, "energy": 2, "rk4": 3, "heun": 4, "rk4_vjp": 5, "relax": 6, "heun_vjp": 7}
+
+    def last_launch_ms(self, kind: str) -> float:
+        """Duration in ms of the last timed launch of one kind (llg_last_launch_ms):
+        'field', 'rhs', 'energy', 'rk4', 'heun', 'rk4_vjp', 'relax' or 'heun_vjp'."""
+        ms = ctypes.c_float()
+        check(_lib.load().llg_last_launch_ms(self._h, self.LAUNCH_MODES[kind], ctypes.byref(ms)), "llg_last_launch_ms")
+        return ms.value
+
     def debug_spin_limit(self, polls: int):
         """Failure-path test hook (llg_debug_spin_limit): group-barrier waits of later
         launches give up after `polls` polls; 0 restores the default."""

@@ -170,6 +170,10 @@ struct llg_disk_s {
     double* hint_dev = nullptr;
     double* hint_pin = nullptr;
     hipEvent_t hint_event = nullptr;
+    static constexpr int N_MODES = 8;
+    hipEvent_t time_ev[N_MODES][2] = {};          // opt-in launch timing (llg_timing), per mode
+    bool time_valid[N_MODES] = {};                // a launch of that mode was timed since enabling
+    bool timing = false;
     int* wg2disk = nullptr;
     int* wg2local = nullptr;
     int n_wg = 0;
@@ -195,6 +199,9 @@ struct llg_disk_s {
         if (hint_pin) (void)hipHostFree(hint_pin);
         if (prm_event) (void)hipEventDestroy(prm_event);
         if (hint_event) (void)hipEventDestroy(hint_event);
+        for (auto& pair : time_ev)
+            for (hipEvent_t e : pair)
+                if (e) (void)hipEventDestroy(e);
     }
     template <typename T>
     int dalloc(T** p, size_t count) {
@@ -745,8 +752,13 @@ int launch(llg_disk h, int mode, float* m, float* out, long long nsteps, unsigne
     a.series = series;
     a.every = (int)every;
     void* args[] = {&a};
+    if (h->timing) HIP_TRY(hipEventRecord(h->time_ev[mode][0], st));
     HIP_TRY(hipLaunchCooperativeKernel(persistent_kernel(mode, h->UG, h->RSEL, h->PMAX, series != nullptr),
                                        dim3(h->n_wg), dim3(WG_THREADS * h->UG), args, dyn, st));
+    if (h->timing) {
+        HIP_TRY(hipEventRecord(h->time_ev[mode][1], st));
+        h->time_valid[mode] = true;
+    }
     if (step_ptr) {
         hipLaunchKernelGGL(advance_u64, dim3(1), dim3(64), 0, st, h->step_dev, (unsigned long long)nsteps);
         HIP_TRY(hipGetLastError());
@@ -894,6 +906,28 @@ int llg_set_on_chip(llg_disk h, int max_P) {
 }
 
 int llg_get_on_chip(llg_disk h) { return h ? h->onchip_pmax : fail(LLG_EINVAL, "null handle"); }
+
+int llg_timing(llg_disk h, int enable) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (enable && !h->time_ev[0][0])
+        for (auto& pair : h->time_ev)
+            for (hipEvent_t& e : pair) HIP_TRY(hipEventCreate(&e));
+    h->timing = enable != 0;
+    for (bool& v : h->time_valid) v = false;
+    return 0;
+}
+
+int llg_last_launch_ms(llg_disk h, int mode, float* ms) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!ms) return fail(LLG_EINVAL, "null output");
+    if (mode < 0 || mode >= llg_disk_s::N_MODES) return fail(LLG_EINVAL, "mode out of range");
+    if (!h->time_valid[mode]) return fail(LLG_EINVAL, "no launch of this mode timed since timing was enabled");
+    HIP_TRY(hipEventSynchronize(h->time_ev[mode][1]));
+    HIP_TRY(hipEventElapsedTime(ms, h->time_ev[mode][0], h->time_ev[mode][1]));
+    return 0;
+}
 
 int llg_debug_spin_limit(llg_disk h, unsigned int polls) {
     if (!h) return fail(LLG_EINVAL, "null handle");
