@@ -247,7 +247,10 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         }
     };
     // all column tiles of this workgroup: z first (it needs only Kzz), while the
-    // x and y columns are still arriving
+    // x and y columns are still arriving.  The kernel spectra are loaded ahead of
+    // the transform before the one that needs them (Kzz with the columns, Kxx,
+    // Kyy and Kxy before the z transform's inverse), so that no memory latency
+    // sits between two transforms of a column.
     auto column_pass_slot = [&]() {
         stage_twiddles<P, R>(stw, ltw, t);
         for (int b = g; b < n_cb; b += G) {
@@ -271,25 +274,29 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                 const int ky = t + j * Tf;
                 return kx * H + (ky <= P / 2 ? ky : P - ky);
             };
+            float kzz[R];
+#pragma unroll
+            for (int j = 0; j < R; ++j) kzz[j] = bld1c(Krs, valid ? (3 * H * H + kidx(j)) * 4 : OOB);
             col_fwd(Z);
+            float kxx[R], kyy[R], kxy[R];
 #pragma unroll
             for (int j = 0; j < R; ++j) {
-                const float kzz = bld1c(Krs, valid ? (3 * H * H + kidx(j)) * 4 : OOB);
-                Z[j] = make_float2(kzz * Z[j].x, kzz * Z[j].y);
+                const int o = kidx(j);
+                kxx[j] = bld1c(Krs, valid ? o * 4 : OOB);
+                kyy[j] = bld1c(Krs, valid ? (H * H + o) * 4 : OOB);
+                kxy[j] = bld1c(Krs, valid ? (2 * H * H + o) * 4 : OOB);
             }
+#pragma unroll
+            for (int j = 0; j < R; ++j) Z[j] = make_float2(kzz[j] * Z[j].x, kzz[j] * Z[j].y);
             col_inv_store(2, kx, valid, Z);
             col_fwd(X);
             col_fwd(Y);
 #pragma unroll
             for (int j = 0; j < R; ++j) {
-                const int o = kidx(j);
-                const float kxx = bld1c(Krs, valid ? o * 4 : OOB);
-                const float kyy = bld1c(Krs, valid ? (H * H + o) * 4 : OOB);
-                const float kxy = bld1c(Krs, valid ? (2 * H * H + o) * 4 : OOB);
-                const float axy = t + j * Tf <= P / 2 ? kxy : -kxy;   // K_xy is odd in ky
+                const float axy = t + j * Tf <= P / 2 ? kxy[j] : -kxy[j];   // K_xy is odd in ky
                 const float2 x = X[j], y = Y[j];
-                X[j] = make_float2(kxx * x.x + axy * y.x, kxx * x.y + axy * y.y);
-                Y[j] = make_float2(axy * x.x + kyy * y.x, axy * x.y + kyy * y.y);
+                X[j] = make_float2(kxx[j] * x.x + axy * y.x, kxx[j] * x.y + axy * y.y);
+                Y[j] = make_float2(axy * x.x + kyy[j] * y.x, axy * x.y + kyy[j] * y.y);
             }
             col_inv_store(0, kx, valid, X);
             col_inv_store(1, kx, valid, Y);
