@@ -478,7 +478,11 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             i = e % HC;
         }
     };
-    auto halo_load = [&](int b, const float* Ys, float (&hv)[IH]) {
+    // Cells outside the disk read as zero: a state this kernel wrote is zero
+    // there already (every stage stores the whole box), so only a caller's
+    // state (MASKED) needs the disk test.
+    auto halo_load_t = [&](auto masked, int b, const float* Ys, float (&hv)[IH]) {
+        constexpr bool MASKED = decltype(masked)::value;
         const __amdgpu_buffer_rsrc_t Yr = make_rsrc(Ys, (unsigned)(3 * DD) * 4u);
 #pragma unroll
         for (int q = 0; q < IH; ++q) {
@@ -486,9 +490,15 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             halo_elem(q, row, i);
             const int c = row / HR, rr = row - c * HR;
             const int j = 2 * b * U - 1 + rr;
-            const bool ok = row < 3 * HR && i < D && j >= 0 && j < D && in_disk(j, i, D);
+            const bool ok = row < 3 * HR && i < D && j >= 0 && j < D && (!MASKED || in_disk(j, i, D));
             hv[q] = bld1(Yr, ok ? (c * DD + j * D + i) * 4 : OOB);
         }
+    };
+    auto halo_load = [&](int b, const float* Ys, float (&hv)[IH], bool masked) {
+        if (masked)
+            halo_load_t(BoolC<true>{}, b, Ys, hv);
+        else
+            halo_load_t(BoolC<false>{}, b, Ys, hv);
     };
     auto halo_store = [&](const float (&hv)[IH]) {
 #pragma unroll
@@ -624,7 +634,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
                 const int j = j0 + r;
-                const bool okc = live && j < D && in_disk(j, i, D);
+                const bool okc = live && j < D;   // values outside the disk are never used
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const int cell = c * DD + j * D + i;
@@ -1332,7 +1342,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         auto row_step = [&](int b, int s, long long n, const float* Ys, float* Yn) {
             float hv[IH];
             SRow sv[IS];
-            halo_load(b, Ys, hv);
+            halo_load(b, Ys, hv, true);
             gather(b, s);
             row_load(b, sv);
             halo_store(hv);
@@ -1348,9 +1358,11 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         // write; a load past the last iteration reads zeros or unused rows)
         auto row_pass = [&](int s, long long n, const float* Ys, float* Yn, bool fwd, bool sample) {
             if (g >= n_rb) return;
+            // the caller's state is read at the first stage of the launch only
+            const bool masked = n == 0 && s == 0;
             float hv[IH];
             SRow sv[IS];
-            halo_load(g, Ys, hv);
+            halo_load(g, Ys, hv, masked);
             row_load(g, sv);
             for (int b = g; b < n_rb; b += G) {
                 gather(b, s);
@@ -1359,7 +1371,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                 if constexpr (SERIES)
                     if (sample) sample_pass(b);
                 cell_update(b, s, n, Yn);
-                halo_load(b + G, Ys, hv);
+                halo_load(b + G, Ys, hv, masked);
                 row_load(b + G, sv);
                 if (fwd) row_forward_store(b);
             }
