@@ -132,7 +132,6 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         uu = (rest / H) * UQ + uq;
     };
     const int n_rb = (d.n_pairs + U - 1) / U;
-    const int n_cb = (H + 3 * U - 1) / (3 * U);   // column tiles of 3U columns (one per transform slot)
     const int n_cb_split = (H + U - 1) / U;       // column tiles of U columns (one wave per component)
     unsigned int epoch = 0;
     // the field kernel serves demag / rhs / energy at run time; the integrators are compiled per mode
@@ -246,60 +245,77 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             wave_sync();
         }
     };
-    // all column tiles of this workgroup: z first (it needs only Kzz), while the
-    // x and y columns are still arriving.  The kernel spectra are loaded ahead of
-    // the transform before the one that needs them (Kzz with the columns, Kxx,
-    // Kyy and Kxy before the z transform's inverse), so that no memory latency
-    // sits between two transforms of a column.
+    // all columns of this workgroup.  At P = 512 (one transform slot per
+    // wavefront) round r of the disk's workgroups takes the G * 3U columns from
+    // r * G * 3U on, dealt to the workgroups in turn, so that the last, partial
+    // round is spread over all of them, and a slot without a column skips it
+    // (the phase has no workgroup barrier); below P = 512 a workgroup takes
+    // tiles of 3U adjacent columns (tile b = g + r G), which measured faster for
+    // the ragged ensemble, and a slot past the last column transforms zeros.
+    // z first (it needs only Kzz), while the x and y columns are still
+    // arriving.  The kernel spectra are loaded ahead of the transform before
+    // the one that needs them (Kzz with the columns, Kxx, Kyy and Kxy before
+    // the z transform's inverse), so that no memory latency sits between two
+    // transforms of a column.
+    auto column_item = [&](int kx, bool valid) {
+        float2 X[R], Y[R], Z[R];
+#pragma unroll
+        for (int j = 0; j < R / 2; ++j) {
+            const int i = t + j * Tf;
+            Z[j] = sld2((valid && i < D) ? soff(2, kx, i) : OOB);
+        }
+#pragma unroll
+        for (int j = 0; j < R / 2; ++j) {
+            const int i = t + j * Tf;
+            const bool ok = valid && i < D;
+            X[j] = sld2(ok ? soff(0, kx, i) : OOB);
+            Y[j] = sld2(ok ? soff(1, kx, i) : OOB);
+        }
+        // kernel spectra at this lane's points: quarter-plane planes 0 = xx, 1 = yy, 2 = xy, 3 = zz
+        auto kidx = [&](int j) {
+            const int ky = t + j * Tf;
+            return kx * H + (ky <= P / 2 ? ky : P - ky);
+        };
+        float kzz[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) kzz[j] = bld1c(Krs, valid ? (3 * H * H + kidx(j)) * 4 : OOB);
+        col_fwd(Z);
+        float kxx[R], kyy[R], kxy[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int o = kidx(j);
+            kxx[j] = bld1c(Krs, valid ? o * 4 : OOB);
+            kyy[j] = bld1c(Krs, valid ? (H * H + o) * 4 : OOB);
+            kxy[j] = bld1c(Krs, valid ? (2 * H * H + o) * 4 : OOB);
+        }
+#pragma unroll
+        for (int j = 0; j < R; ++j) Z[j] = make_float2(kzz[j] * Z[j].x, kzz[j] * Z[j].y);
+        col_inv_store(2, kx, valid, Z);
+        col_fwd(X);
+        col_fwd(Y);
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const float axy = t + j * Tf <= P / 2 ? kxy[j] : -kxy[j];   // K_xy is odd in ky
+            const float2 x = X[j], y = Y[j];
+            X[j] = make_float2(kxx[j] * x.x + axy * y.x, kxx[j] * x.y + axy * y.y);
+            Y[j] = make_float2(axy * x.x + kyy[j] * y.x, axy * x.y + kyy[j] * y.y);
+        }
+        col_inv_store(0, kx, valid, X);
+        col_inv_store(1, kx, valid, Y);
+    };
     auto column_pass_slot = [&]() {
         stage_twiddles<P, R>(stw, ltw, t);
-        for (int b = g; b < n_cb; b += G) {
-            const int kx = b * NSLOT + slot;
-            const bool valid = kx < H;
-            float2 X[R], Y[R], Z[R];
-#pragma unroll
-            for (int j = 0; j < R / 2; ++j) {
-                const int i = t + j * Tf;
-                Z[j] = sld2((valid && i < D) ? soff(2, kx, i) : OOB);
+        if constexpr (P == 512) {
+            for (int base = 0; base < H; base += G * NSLOT) {
+                const int kx = base + slot * G + g;
+                if (kx < H) column_item(kx, true);
             }
-#pragma unroll
-            for (int j = 0; j < R / 2; ++j) {
-                const int i = t + j * Tf;
-                const bool ok = valid && i < D;
-                X[j] = sld2(ok ? soff(0, kx, i) : OOB);
-                Y[j] = sld2(ok ? soff(1, kx, i) : OOB);
+        } else {
+            const int n_cb = (H + NSLOT - 1) / NSLOT;
+            for (int b = g; b < n_cb; b += G) {
+                const int kx = b * NSLOT + slot;
+                column_item(kx, kx < H);
             }
-            // kernel spectra at this lane's points: quarter-plane planes 0 = xx, 1 = yy, 2 = xy, 3 = zz
-            auto kidx = [&](int j) {
-                const int ky = t + j * Tf;
-                return kx * H + (ky <= P / 2 ? ky : P - ky);
-            };
-            float kzz[R];
-#pragma unroll
-            for (int j = 0; j < R; ++j) kzz[j] = bld1c(Krs, valid ? (3 * H * H + kidx(j)) * 4 : OOB);
-            col_fwd(Z);
-            float kxx[R], kyy[R], kxy[R];
-#pragma unroll
-            for (int j = 0; j < R; ++j) {
-                const int o = kidx(j);
-                kxx[j] = bld1c(Krs, valid ? o * 4 : OOB);
-                kyy[j] = bld1c(Krs, valid ? (H * H + o) * 4 : OOB);
-                kxy[j] = bld1c(Krs, valid ? (2 * H * H + o) * 4 : OOB);
-            }
-#pragma unroll
-            for (int j = 0; j < R; ++j) Z[j] = make_float2(kzz[j] * Z[j].x, kzz[j] * Z[j].y);
-            col_inv_store(2, kx, valid, Z);
-            col_fwd(X);
-            col_fwd(Y);
-#pragma unroll
-            for (int j = 0; j < R; ++j) {
-                const float axy = t + j * Tf <= P / 2 ? kxy[j] : -kxy[j];   // K_xy is odd in ky
-                const float2 x = X[j], y = Y[j];
-                X[j] = make_float2(kxx[j] * x.x + axy * y.x, kxx[j] * x.y + axy * y.y);
-                Y[j] = make_float2(axy * x.x + kyy[j] * y.x, axy * x.y + kyy[j] * y.y);
-            }
-            col_inv_store(0, kx, valid, X);
-            col_inv_store(1, kx, valid, Y);
         }
     };
 
