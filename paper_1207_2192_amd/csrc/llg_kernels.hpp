@@ -251,7 +251,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     // round is spread over all of them, and a slot without a column skips it
     // (the phase has no workgroup barrier); below P = 512 a workgroup takes
     // tiles of 3U adjacent columns (tile b = g + r G), which measured faster for
-    // the ragged ensemble, and a slot past the last column transforms zeros.
+    // the ragged ensemble, and a slot past the last column skips the tile.
     // z first (it needs only Kzz), while the x and y columns are still
     // arriving.  The kernel spectra are loaded ahead of the transform before
     // the one that needs them (Kzz with the columns, Kxx, Kyy and Kxy before
@@ -314,7 +314,7 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             const int n_cb = (H + NSLOT - 1) / NSLOT;
             for (int b = g; b < n_cb; b += G) {
                 const int kx = b * NSLOT + slot;
-                column_item(kx, kx < H);
+                if (kx < H) column_item(kx, true);
             }
         }
     };
