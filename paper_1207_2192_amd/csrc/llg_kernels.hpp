@@ -1368,8 +1368,10 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
 
         // all row iterations of a stage: the staged rows and row spectra of the
         // next iteration are loaded after the cell update of the current one, so
-        // that they are in flight during its forward transforms and stores; the
-        // start state and accumulator are loaded at the top of the iteration
+        // that they are in flight during its forward transforms and stores (at
+        // P = 512 the staged rows are loaded before the cell update, so that
+        // fewer loads queue behind its state stores); the start state and
+        // accumulator are loaded at the top of the iteration
         // (iterations touch disjoint rows of the spectra and of the states they
         // write; a load past the last iteration reads zeros or unused rows)
         auto row_pass = [&](int s, long long n, const float* Ys, float* Yn, bool fwd, bool sample) {
@@ -1386,8 +1388,9 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
                 row_unpack_inverse(sv);
                 if constexpr (SERIES)
                     if (sample) sample_pass(b);
+                if constexpr (P == 512) halo_load(b + G, Ys, hv, masked);
                 cell_update(b, s, n, Yn);
-                halo_load(b + G, Ys, hv, masked);
+                if constexpr (P != 512) halo_load(b + G, Ys, hv, masked);
                 row_load(b + G, sv);
                 if (fwd) row_forward_store(b);
             }
