@@ -19,13 +19,13 @@ constexpr int LDS_FFT = 3 * 64 * MAX_R * 9 / 8 + 3 * 4 * 32;   // float2 per gro
 // writes whole segments.
 constexpr int SB = 8;
 
-// Per-disk descriptor (device memory, written once by the host).
 // A compile-time flag passed as a value (for generic lambdas).
 template <bool B>
 struct BoolC {
     static constexpr bool value = B;
 };
 
+// Per-disk descriptor (device memory, written once by the host).
 struct DiskDesc {
     int D, P, H, Dp;          // box, FFT size, P/2+1, D rounded up to a multiple of SB
     int n_pairs, G, n_cells, k;  // row pairs, workgroups, masked cells, index in the batch

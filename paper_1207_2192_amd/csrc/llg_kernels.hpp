@@ -226,21 +226,21 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             wave_sync();
         }
     };
-    auto col_inv_store = [&](int c, int kx, bool valid, float2 (&v)[R]) {
+    auto col_inv_store = [&](int c, int kx, float2 (&v)[R]) {
         __builtin_amdgcn_sched_barrier(0);
         if constexpr (KEEP) {
             fft_run<P, R, true, true>(v, mybuf, ltw, t, &stw);   // v[j] = column value at row t + j*Tf
 #pragma unroll
             for (int j = 0; j < R / 2; ++j) {
                 const int i = t + j * Tf;
-                sst2((valid && i < D) ? soff(c, kx, i) : OOB, v[j]);
+                sst2(i < D ? soff(c, kx, i) : OOB, v[j]);
             }
         } else {
             fft_run<P, R, true, false, false, false, true>(v, mybuf, ltw, t, &stw);
 #pragma unroll
             for (int j = 0; j < R / 2; ++j) {
                 const int i = t + j * Tf;
-                sst2((valid && i < D) ? soff(c, kx, i) : OOB, mybuf[padb(i)]);
+                sst2(i < D ? soff(c, kx, i) : OOB, mybuf[padb(i)]);
             }
             wave_sync();
         }
@@ -252,22 +252,23 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
     // (the phase has no workgroup barrier); below P = 512 a workgroup takes
     // tiles of 3U adjacent columns (tile b = g + r G), which measured faster for
     // the ragged ensemble, and a slot past the last column skips the tile.
+    // Either way every column a slot transforms is a real one (kx < H).
     // z first (it needs only Kzz), while the x and y columns are still
     // arriving.  The kernel spectra are loaded ahead of the transform before
     // the one that needs them (Kzz with the columns, Kxx, Kyy and Kxy before
     // the z transform's inverse), so that no memory latency sits between two
     // transforms of a column.
-    auto column_item = [&](int kx, bool valid) {
+    auto column_item = [&](int kx) {
         float2 X[R], Y[R], Z[R];
 #pragma unroll
         for (int j = 0; j < R / 2; ++j) {
             const int i = t + j * Tf;
-            Z[j] = sld2((valid && i < D) ? soff(2, kx, i) : OOB);
+            Z[j] = sld2(i < D ? soff(2, kx, i) : OOB);
         }
 #pragma unroll
         for (int j = 0; j < R / 2; ++j) {
             const int i = t + j * Tf;
-            const bool ok = valid && i < D;
+            const bool ok = i < D;
             X[j] = sld2(ok ? soff(0, kx, i) : OOB);
             Y[j] = sld2(ok ? soff(1, kx, i) : OOB);
         }
@@ -278,19 +279,19 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
         };
         float kzz[R];
 #pragma unroll
-        for (int j = 0; j < R; ++j) kzz[j] = bld1c(Krs, valid ? (3 * H * H + kidx(j)) * 4 : OOB);
+        for (int j = 0; j < R; ++j) kzz[j] = bld1c(Krs, (3 * H * H + kidx(j)) * 4);
         col_fwd(Z);
         float kxx[R], kyy[R], kxy[R];
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const int o = kidx(j);
-            kxx[j] = bld1c(Krs, valid ? o * 4 : OOB);
-            kyy[j] = bld1c(Krs, valid ? (H * H + o) * 4 : OOB);
-            kxy[j] = bld1c(Krs, valid ? (2 * H * H + o) * 4 : OOB);
+            kxx[j] = bld1c(Krs, o * 4);
+            kyy[j] = bld1c(Krs, (H * H + o) * 4);
+            kxy[j] = bld1c(Krs, (2 * H * H + o) * 4);
         }
 #pragma unroll
         for (int j = 0; j < R; ++j) Z[j] = make_float2(kzz[j] * Z[j].x, kzz[j] * Z[j].y);
-        col_inv_store(2, kx, valid, Z);
+        col_inv_store(2, kx, Z);
         col_fwd(X);
         col_fwd(Y);
 #pragma unroll
@@ -300,21 +301,21 @@ __device__ __forceinline__ void run_disk(const KArgs& a, const DiskDesc& d, cons
             X[j] = make_float2(kxx[j] * x.x + axy * y.x, kxx[j] * x.y + axy * y.y);
             Y[j] = make_float2(axy * x.x + kyy[j] * y.x, axy * x.y + kyy[j] * y.y);
         }
-        col_inv_store(0, kx, valid, X);
-        col_inv_store(1, kx, valid, Y);
+        col_inv_store(0, kx, X);
+        col_inv_store(1, kx, Y);
     };
     auto column_pass_slot = [&]() {
         stage_twiddles<P, R>(stw, ltw, t);
         if constexpr (P == 512) {
             for (int base = 0; base < H; base += G * NSLOT) {
                 const int kx = base + slot * G + g;
-                if (kx < H) column_item(kx, true);
+                if (kx < H) column_item(kx);
             }
         } else {
             const int n_cb = (H + NSLOT - 1) / NSLOT;
             for (int b = g; b < n_cb; b += G) {
                 const int kx = b * NSLOT + slot;
-                if (kx < H) column_item(kx, true);
+                if (kx < H) column_item(kx);
             }
         }
     };
